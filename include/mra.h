@@ -1,0 +1,141 @@
+/*
+ * mra.h -- C ABI of the MI355X (gfx950) library for the multi-resolution
+ * approximation (MRA) of a Gaussian process: partition build, log-likelihood
+ * and kriging.
+ *
+ * The method is the one whose CPU implementation is described by Huang, Blake
+ * & Hammerling ("Pushing the Limit: A Hybrid Parallel Implementation of the
+ * Multi-resolution Approximation for Massive Data"):
+ *   - the process and its remainder covariances, Sec. 1.1;
+ *   - the J-ary partition, half-open regions, the one-percent extension of
+ *     the root and the grid knots, Sec. 1.2 and Appendix A;
+ *   - the calculation modes (build structure, likelihood, prediction) and the
+ *     covariance parameters sill/range/nugget, Sec. 2.2 (user parameters);
+ *   - the data file layout (n, then longitudes, latitudes, values as 64-bit
+ *     reals), Sec. 2.2.
+ *
+ * All arithmetic is FP64.  Status codes are returned; no exception crosses
+ * the ABI.  mra_last_error() gives a thread-local message for the last
+ * failing call on the calling thread.
+ */
+#ifndef MRA_H
+#define MRA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mra_tree mra_tree;
+
+/* status codes */
+#define MRA_OK 0
+#define MRA_EINVAL (-1)  /* invalid argument */
+#define MRA_ENOTPD (-2)  /* a Cholesky pivot was not positive: matrix not positive definite */
+#define MRA_ENOMEM (-3)  /* device or host allocation failed */
+#define MRA_EDEVICE (-4) /* HIP runtime error, or no gfx950 device */
+#define MRA_EDOMAIN (-5) /* a location lies outside the root region */
+
+/* covariance families; distance t = |a - b| / range (Euclidean, in the plane)
+ *   MRA_EXP           : sill * exp(-t)                  (the paper's exponential)
+ *   MRA_MATERN nu=0.5 : sill * exp(-t)
+ *   MRA_MATERN nu=1.5 : sill * (1 + t) * exp(-t)                                  */
+#define MRA_EXP 0
+#define MRA_MATERN 1
+
+/* mra_build_tree flags */
+#define MRA_DEVICE_PTRS (1u << 0)  /* x, y, z are device pointers (else host) */
+#define MRA_FOLD_GRAM (1u << 4)    /* fold every region in knot space (Gram form) */
+#define MRA_FOLD_FACTOR (1u << 5)  /* fold in observation space wherever scratch allows */
+
+/*
+ * Build the multi-resolution partition (Sec. 1.2).
+ *   x, y, z : n locations and values (host memory, or device memory with
+ *             MRA_DEVICE_PTRS).  Read during the call only; the library keeps
+ *             its own device copy, so the caller may free them on return.
+ *             A NaN value marks a location without an observation: it is left
+ *             out of the likelihood.  Non-finite locations -> MRA_EINVAL.
+ *   J       : 2 (split the longer side, x on a tie) or 4 (halve both sides).
+ *   r       : requested knots per region above the finest level; the knots
+ *             form a ceil(sqrt r) x floor(r / ceil(sqrt r)) grid, so
+ *             r_hat = that product knots are placed.  This build supports
+ *             r_hat <= 64 (MRA_EINVAL beyond).
+ *   M       : number of levels, >= 1.  The finest level holds the observations
+ *             as its knots.
+ *   offset  : knot offset as a fraction of the region side; <= 0 selects the
+ *             default e/100 (Sec. 1.2, Appendix A).
+ *   domain4 : {xmin, xmax, ymin, ymax} of the root region, used verbatim, or
+ *             NULL for the data bounding box with its right and top sides
+ *             pushed out by one percent of the side length.  An observation
+ *             outside the half-open root region -> MRA_EDOMAIN.
+ *   out     : receives an opaque, immutable, library-owned handle; release it
+ *             with mra_free_tree.
+ * Observations that coincide exactly with a knot of an ancestor region above
+ * the finest level are dropped (Sec. 1.2).  Requires a gfx950 device (the
+ * current HIP device); the tree's device arrays live on it.
+ */
+int mra_build_tree(const double *x, const double *y, const double *z, int64_t n, int J, int r, int M,
+                   double offset, uint32_t flags, const double *domain4, mra_tree **out);
+
+/*
+ * MRA log-likelihood for B covariance-parameter vectors (likelihood mode,
+ * Sec. 2.2): loglik[b] = log N(z; 0, Sigma_MRA(theta_b) + tau_b I), where
+ * Sigma_MRA is the covariance of tau_1 + ... + tau_M of Sec. 1.1 at the
+ * observations, including the -n/2 log(2 pi) constant.
+ *   family, nu : MRA_EXP (nu ignored) or MRA_MATERN with nu = 0.5 or 1.5.
+ *   theta      : B x 3 row-major {sill alpha, range beta, nugget tau}, all > 0.
+ *   loglik     : B outputs.  theta and loglik are both host or both device
+ *                pointers.
+ *   stream     : hipStream_t (NULL = the null stream).  With device pointers
+ *                the call is asynchronous on the stream; with host pointers it
+ *                returns after the results are written.
+ * The tree is read-only: concurrent calls on different streams are allowed.
+ * Errors: MRA_EINVAL (bad family/nu/theta), MRA_ENOTPD (message names theta
+ * index, level and region), MRA_ENOMEM, MRA_EDEVICE.
+ */
+int mra_loglik(const mra_tree *tree, int family, double nu, const double *theta, int64_t B,
+               double *loglik, void *stream);
+
+/*
+ * Kriging (prediction mode, Sec. 2.2): posterior mean and variance of the
+ * latent process X (no nugget) at np locations given the tree's observations.
+ * Each location joins the finest-level region that contains it.
+ *   theta    : 3 values {alpha, beta, tau}.
+ *   px, py   : np locations; mean, var : np outputs.  All host or all device
+ *              pointers (same memory space).
+ * A location outside the root region -> MRA_EDOMAIN (nothing is clamped).
+ */
+int mra_predict(const mra_tree *tree, int family, double nu, const double *theta, const double *px,
+                const double *py, int64_t np, double *mean, double *var, void *stream);
+
+/* Release a tree and its device memory.  NULL is allowed. */
+void mra_free_tree(mra_tree *tree);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *mra_last_error(void);
+
+typedef struct mra_info {
+    int64_t n_in, n_nan, n_elim, n_used; /* inputs, NaN values, knot coincidences dropped, used */
+    int32_t J, M, r, r_hat, P;           /* P = r_hat padded to the kernel tile (16, 32 or 64) */
+    int64_t n_regions, n_leaves;
+    int64_t leaf_min, leaf_max;          /* observations per finest-level region */
+    int64_t n_gram_regions;              /* regions folded in knot space */
+} mra_info;
+
+/* Structure summary (the build-structure-only mode of Sec. 2.2). */
+int mra_tree_info(const mra_tree *tree, mra_info *info);
+
+/*
+ * Copy of the tree's used observations in the library's internal order
+ * (grouped by finest-level region, input order kept inside a region), the
+ * input index of each, and the per-leaf offsets (n_leaves + 1).  Host
+ * pointers; any may be NULL.
+ */
+int mra_tree_arrays(const mra_tree *tree, double *x, double *y, double *z, int64_t *orig,
+                    int64_t *leaf_off);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRA_H */

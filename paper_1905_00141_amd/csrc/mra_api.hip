@@ -1,0 +1,391 @@
+// C-ABI entry points of the MRA library: tree upload, execution plan,
+// memory sizing and the per-level launch schedule.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mra.h"
+#include "mra_internal.h"
+#include "mra_kernels.h"
+
+namespace mra {
+hipError_t launch_prior(const KArgs& a, int grid, hipStream_t st);
+hipError_t launch_leaf(const KArgs& a, int grid, hipStream_t st);
+hipError_t launch_fold_factor(const KArgs& a, int grid, hipStream_t st);
+hipError_t launch_fold_gram(const KArgs& a, int grid, hipStream_t st);
+hipError_t launch_final(const KArgs& a, int64_t nreg, int root_gram, hipStream_t st);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st);
+}  // namespace mra
+
+using namespace mra;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+// Largest observation count a region may hold and still fold in observation
+// space (its scratch matrix is that count squared).
+constexpr int64_t FACTOR_FOLD_MAX = 512;
+
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+template <class T>
+int upload(T** dst, const std::vector<T>& v) {
+    *dst = nullptr;
+    const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+    if (hipMalloc(reinterpret_cast<void**>(dst), bytes) != hipSuccess) return MRA_ENOMEM;
+    if (!v.empty() && hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return MRA_EDEVICE;
+    return MRA_OK;
+}
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice;
+}
+
+}  // namespace
+
+struct mra_tree {
+    HostTree h;
+    int device = 0;
+    uint32_t flags = 0;
+    // device copies
+    double *d_x = nullptr, *d_y = nullptr, *d_z = nullptr, *d_box = nullptr;
+    int64_t *d_obs_lo = nullptr, *d_obs_hi = nullptr, *d_vst_off = nullptr, *d_gram_off = nullptr;
+    int8_t* d_form = nullptr;
+    // plan
+    std::vector<int8_t> form;
+    std::vector<int64_t> vst_off, gram_off;
+    int64_t vst_size = 0, gram_size = 0;
+    int WF = 1, WFs = 2;
+    std::vector<std::vector<int>> prior_tasks, factor_tasks, gram_tasks;  // index by level (1..M-1)
+    std::vector<int> leaf_tasks;
+    std::vector<int*> d_prior, d_factor, d_gramt;
+    int* d_leaf = nullptr;
+    int64_t scratch_leaf = 0, scratch_fold = 0;  // doubles per workgroup slot
+    int root_gram = 0;
+    int64_t n_gram = 0, leaf_min = 0, leaf_max = 0;
+
+    ~mra_tree() {
+        void* ps[] = {d_x, d_y, d_z, d_box, d_obs_lo, d_obs_hi, d_vst_off, d_gram_off, d_form, d_leaf};
+        for (void* p : ps) if (p) (void)hipFree(p);
+        for (auto* v : {&d_prior, &d_factor, &d_gramt})
+            for (int* p : *v) if (p) (void)hipFree(p);
+    }
+};
+
+extern "C" const char* mra_last_error(void) { return g_err.c_str(); }
+
+extern "C" void mra_free_tree(mra_tree* t) { delete t; }
+
+static int check_device() {
+    int dev = 0, cnt = 0;
+    if (hipGetDeviceCount(&cnt) != hipSuccess || cnt == 0) {
+        (void)hipGetLastError();
+        return fail(MRA_EDEVICE, "no HIP device");
+    }
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MRA_EDEVICE, "hipGetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(MRA_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(MRA_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    return MRA_OK;
+}
+
+extern "C" int mra_build_tree(const double* x, const double* y, const double* z, int64_t n, int J, int r, int M,
+                              double offset, uint32_t flags, const double* domain4, mra_tree** out) {
+    if (!out) return fail(MRA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n > 0 && (!x || !y || !z)) return fail(MRA_EINVAL, "x, y, z must not be NULL");
+    if (n > (int64_t(1) << 31) - 1) return fail(MRA_EINVAL, "n must fit in 31 bits");
+    int rc = check_device();
+    if (rc) return rc;
+    std::vector<double> hx, hy, hz;
+    const double *px = x, *py = y, *pz = z;
+    if (flags & MRA_DEVICE_PTRS) {
+        hx.resize(n); hy.resize(n); hz.resize(n);
+        if (n > 0 && (hipMemcpy(hx.data(), x, n * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+                      hipMemcpy(hy.data(), y, n * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+                      hipMemcpy(hz.data(), z, n * 8, hipMemcpyDeviceToHost) != hipSuccess))
+            return fail(MRA_EDEVICE, "copy of device inputs failed");
+        px = hx.data(); py = hy.data(); pz = hz.data();
+    }
+    auto* t = new mra_tree();
+    t->flags = flags;
+    (void)hipGetDevice(&t->device);
+    std::string err;
+    rc = build_host_tree(px, py, pz, n, J, r, M, offset, domain4, t->h, err);
+    if (rc) { delete t; return fail(rc, err); }
+    const HostTree& h = t->h;
+    const int P = h.P;
+
+    // plan: fold form of every non-leaf region, storage offsets, task lists
+    t->form.assign(h.nreg, FOLD_FACTOR);
+    t->vst_off.assign(h.nreg, -1);
+    t->gram_off.assign(h.nreg, -1);
+    t->prior_tasks.assign(M, {});
+    t->factor_tasks.assign(M, {});
+    t->gram_tasks.assign(M, {});
+    int64_t vo = 0, go = 0;
+    for (int m = 1; m < M; ++m) {
+        const int64_t thr = (flags & MRA_FOLD_GRAM) ? 0
+                            : (flags & MRA_FOLD_FACTOR) ? 4096
+                            : std::min<int64_t>(int64_t(m - 1) * P + 1, FACTOR_FOLD_MAX);
+        const int64_t D = int64_t(m) * P + 1;
+        for (int64_t g = h.lvl_start[m - 1]; g < h.lvl_start[m]; ++g) {
+            const int64_t np = h.obs_hi[g] - h.obs_lo[g];
+            if (np == 0) continue;  // empty subtree: contributes nothing
+            t->prior_tasks[m].push_back(int(g));
+            t->vst_off[g] = vo;
+            vo += int64_t(m) * P * P;
+            if (np <= thr) {
+                t->form[g] = FOLD_FACTOR;
+                t->factor_tasks[m].push_back(int(g));
+                t->scratch_fold = std::max(t->scratch_fold, np * np);
+            } else {
+                t->form[g] = FOLD_GRAM;
+                t->gram_tasks[m].push_back(int(g));
+                t->gram_off[g] = go;
+                go += D * D;
+                ++t->n_gram;
+            }
+        }
+    }
+    t->vst_size = std::max<int64_t>(vo, 1);
+    t->gram_size = std::max<int64_t>(go, 1);
+    t->leaf_min = INT64_MAX;
+    for (int64_t g = h.lvl_start[M - 1]; g < h.lvl_start[M]; ++g) {
+        const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
+        t->leaf_min = std::min(t->leaf_min, nc);
+        t->leaf_max = std::max(t->leaf_max, nc);
+        if (nc > 0) {
+            t->leaf_tasks.push_back(int(g));
+            t->scratch_leaf = std::max(t->scratch_leaf, nc * nc);
+        }
+    }
+    if (t->leaf_min == INT64_MAX) t->leaf_min = 0;
+    t->WF = (M - 1) * P + 1;
+    t->WFs = (t->WF + 3) & ~3;
+    t->root_gram = (M > 1 && t->form[0] == FOLD_GRAM) ? 1 : 0;
+
+    // device copies
+    std::vector<int64_t> lo(h.obs_lo), hi(h.obs_hi);
+    if ((rc = upload(&t->d_x, h.x)) || (rc = upload(&t->d_y, h.y)) || (rc = upload(&t->d_z, h.z)) ||
+        (rc = upload(&t->d_box, h.box)) || (rc = upload(&t->d_obs_lo, lo)) || (rc = upload(&t->d_obs_hi, hi)) ||
+        (rc = upload(&t->d_vst_off, t->vst_off)) || (rc = upload(&t->d_gram_off, t->gram_off)) ||
+        (rc = upload(&t->d_form, t->form)) || (rc = upload(&t->d_leaf, t->leaf_tasks))) {
+        delete t;
+        return fail(rc, "device allocation or copy failed while uploading the tree");
+    }
+    t->d_prior.assign(M, nullptr);
+    t->d_factor.assign(M, nullptr);
+    t->d_gramt.assign(M, nullptr);
+    for (int m = 1; m < M; ++m)
+        if ((rc = upload(&t->d_prior[m], t->prior_tasks[m])) || (rc = upload(&t->d_factor[m], t->factor_tasks[m])) ||
+            (rc = upload(&t->d_gramt[m], t->gram_tasks[m]))) {
+            delete t;
+            return fail(rc, "device allocation failed for task lists");
+        }
+    *out = t;
+    return MRA_OK;
+}
+
+extern "C" int mra_tree_info(const mra_tree* t, mra_info* info) {
+    if (!t || !info) return fail(MRA_EINVAL, "NULL argument");
+    const HostTree& h = t->h;
+    info->n_in = h.n_in; info->n_nan = h.n_nan; info->n_elim = h.n_elim; info->n_used = h.n_used;
+    info->J = h.J; info->M = h.M; info->r = h.r; info->r_hat = h.rhat; info->P = h.P;
+    info->n_regions = h.nreg; info->n_leaves = h.nleaf;
+    info->leaf_min = t->leaf_min; info->leaf_max = t->leaf_max;
+    info->n_gram_regions = t->n_gram;
+    return MRA_OK;
+}
+
+extern "C" int mra_tree_arrays(const mra_tree* t, double* x, double* y, double* z, int64_t* orig,
+                               int64_t* leaf_off) {
+    if (!t) return fail(MRA_EINVAL, "NULL tree");
+    const HostTree& h = t->h;
+    const size_t n = size_t(h.n_used);
+    if (x) std::memcpy(x, h.x.data(), n * 8);
+    if (y) std::memcpy(y, h.y.data(), n * 8);
+    if (z) std::memcpy(z, h.z.data(), n * 8);
+    if (orig) std::memcpy(orig, h.orig.data(), n * 8);
+    if (leaf_off) {
+        const int64_t l0 = h.lvl_start[h.M - 1];
+        for (int64_t k = 0; k < h.nleaf; ++k) leaf_off[k] = h.obs_lo[l0 + k];
+        leaf_off[h.nleaf] = h.n_used;
+    }
+    return MRA_OK;
+}
+
+static int smooth_of(int family, double nu, int* smooth) {
+    if (family == MRA_EXP) { *smooth = 0; return MRA_OK; }
+    if (family == MRA_MATERN && nu == 0.5) { *smooth = 0; return MRA_OK; }
+    if (family == MRA_MATERN && nu == 1.5) { *smooth = 1; return MRA_OK; }
+    return fail(MRA_EINVAL, "family must be MRA_EXP or MRA_MATERN with nu 0.5 or 1.5");
+}
+
+static int region_level(const HostTree& h, int64_t g) {
+    for (int m = 1; m <= h.M; ++m) if (g < h.lvl_start[m]) return m;
+    return h.M;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) { rc = fail(MRA_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); goto done; } \
+    } while (0)
+
+extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double* theta, int64_t B,
+                          double* loglik, void* stream) {
+    if (!t || !theta || !loglik || B < 1) return fail(MRA_EINVAL, "NULL argument or B < 1");
+    int smooth = 0;
+    int rc = smooth_of(family, nu, &smooth);
+    if (rc) return rc;
+    const HostTree& h = t->h;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const bool dev = is_device_ptr(theta);
+    if (dev != is_device_ptr(loglik)) return fail(MRA_EINVAL, "theta and loglik must be in the same memory space");
+    std::vector<double> th(3 * B);
+    if (dev) {
+        if (hipMemcpy(th.data(), theta, 3 * B * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(MRA_EDEVICE, "theta copy failed");
+    } else {
+        std::memcpy(th.data(), theta, 3 * B * 8);
+    }
+    for (int64_t b = 0; b < B; ++b)
+        if (!(th[3 * b] > 0.0) || !(th[3 * b + 1] > 0.0) || !(th[3 * b + 2] > 0.0) || !std::isfinite(th[3 * b]) ||
+            !std::isfinite(th[3 * b + 1]) || !std::isfinite(th[3 * b + 2]))
+            return fail(MRA_EINVAL, "theta " + std::to_string(b) + ": alpha, beta, tau must be finite and > 0");
+
+    const int M = h.M, P = h.P;
+    // per-theta device footprint (doubles)
+    const int64_t F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
+    const int64_t per_theta = t->vst_size + F_stride + t->gram_size + h.nreg;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(MRA_EDEVICE, "hipMemGetInfo failed");
+    const double budget = 0.55 * double(free_b) / 8.0;  // doubles
+    const int64_t scratch_per = std::max<int64_t>({t->scratch_leaf, t->scratch_fold, 1});
+    int64_t nslot = std::min<int64_t>(2048, std::max<int64_t>(1, int64_t(0.25 * budget / double(scratch_per))));
+    const double left = budget - double(nslot) * double(scratch_per);
+    int64_t Bc = std::min<int64_t>(B, int64_t(left / double(per_theta)));
+    if (Bc < 1) return fail(MRA_ENOMEM, "not enough device memory for one theta");
+
+    double *d_th = nullptr, *d_out = nullptr, *vst = nullptr, *F = nullptr, *gram = nullptr, *dval = nullptr,
+           *scratch = nullptr;
+    int* status = nullptr;
+    std::vector<int> hstatus;
+    KArgs a{};
+    const int64_t nprev_theta = 0;
+    (void)nprev_theta;
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&vst), Bc * t->vst_size * 8, st));
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&F), Bc * F_stride * 8, st));
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&gram), Bc * t->gram_size * 8, st));
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&dval), Bc * h.nreg * 8, st));
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&scratch), nslot * scratch_per * 8, st));
+    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&status), B * sizeof(int), st));
+    if (!dev) {
+        HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&d_th), 3 * B * 8, st));
+        HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&d_out), B * 8, st));
+        HIPCHK(hipMemcpyAsync(d_th, theta, 3 * B * 8, hipMemcpyHostToDevice, st));
+    } else {
+        d_th = const_cast<double*>(theta);
+        d_out = loglik;
+    }
+    HIPCHK(launch_fill_int(status, B, 0, st));
+
+    a.x = t->d_x; a.y = t->d_y; a.z = t->d_z; a.box = t->d_box;
+    a.obs_lo = t->d_obs_lo; a.obs_hi = t->d_obs_hi;
+    a.vst_off = t->d_vst_off; a.gram_off = t->d_gram_off; a.form = t->d_form;
+    for (int m = 0; m <= M && m <= MAXL; ++m) a.lvl[m] = h.lvl_start[m];
+    a.J = h.J; a.M = M; a.nx = h.nx; a.ny = h.ny; a.rhat = h.rhat; a.P = P; a.WF = t->WF; a.WFs = t->WFs;
+    a.offset = h.offset; a.smooth = smooth;
+    a.vst = vst; a.vst_stride = t->vst_size;
+    a.F = F; a.F_stride = F_stride;
+    a.gram = gram; a.gram_stride = t->gram_size;
+    a.dval = dval; a.d_stride = h.nreg;
+    a.scratch = scratch; a.scratch_stride = scratch_per;
+    a.n_used = double(h.n_used);
+
+    for (int64_t b0 = 0; b0 < B; b0 += Bc) {
+        const int nb = int(std::min<int64_t>(Bc, B - b0));
+        a.theta = d_th + 3 * b0;
+        a.ntheta = nb;
+        a.status = status + b0;
+        a.out = d_out + b0;
+        HIPCHK(launch_fill(dval, int64_t(nb) * h.nreg, 0.0, st));
+        for (int m = 1; m < M; ++m) {
+            a.level = m;
+            a.tasks = t->d_prior[m];
+            a.ntasks = int64_t(t->prior_tasks[m].size());
+            if (a.ntasks == 0) continue;
+            const int64_t tot = a.ntasks * nb;
+            HIPCHK(launch_prior(a, int(std::min<int64_t>(tot, 1 << 16)), st));
+        }
+        a.level = M;
+        a.tasks = t->d_leaf;
+        a.ntasks = int64_t(t->leaf_tasks.size());
+        if (a.ntasks > 0) HIPCHK(launch_leaf(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st));
+        for (int m = M - 1; m >= 1; --m) {
+            a.level = m;
+            a.tasks = t->d_factor[m];
+            a.ntasks = int64_t(t->factor_tasks[m].size());
+            if (a.ntasks > 0) HIPCHK(launch_fold_factor(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st));
+            a.tasks = t->d_gramt[m];
+            a.ntasks = int64_t(t->gram_tasks[m].size());
+            if (a.ntasks > 0) HIPCHK(launch_fold_gram(a, int(std::min<int64_t>(a.ntasks * nb, 1 << 16)), st));
+        }
+        HIPCHK(launch_final(a, h.nreg, t->root_gram, st));
+    }
+    if (!dev) {
+        HIPCHK(hipMemcpyAsync(loglik, d_out, B * 8, hipMemcpyDeviceToHost, st));
+        hstatus.resize(B);
+        HIPCHK(hipMemcpyAsync(hstatus.data(), status, B * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int64_t b = 0; b < B; ++b)
+            if (hstatus[b] != 0) {
+                const int64_t g = hstatus[b] - 1;
+                const int lev = region_level(h, g);
+                rc = fail(MRA_ENOTPD, "not positive definite: theta " + std::to_string(b) + ", level " +
+                                          std::to_string(lev) + ", region " + std::to_string(g - h.lvl_start[lev - 1]));
+                break;
+            }
+    }
+done:
+    for (void* p : {static_cast<void*>(vst), static_cast<void*>(F), static_cast<void*>(gram),
+                    static_cast<void*>(dval), static_cast<void*>(scratch), static_cast<void*>(status)})
+        if (p) (void)hipFreeAsync(p, st);
+    if (!dev) {
+        if (d_th) (void)hipFreeAsync(d_th, st);
+        if (d_out) (void)hipFreeAsync(d_out, st);
+        (void)hipStreamSynchronize(st);
+    }
+    return rc;
+}
+
+extern "C" int mra_predict(const mra_tree* t, int family, double nu, const double* theta, const double* px,
+                           const double* py, int64_t np, double* mean, double* var, void* stream) {
+    (void)t; (void)family; (void)nu; (void)theta; (void)px; (void)py; (void)np; (void)mean; (void)var;
+    (void)stream;
+    return fail(MRA_EINVAL, "mra_predict is not available in this build yet");
+}

@@ -1,0 +1,33 @@
+// Internal declarations shared by the host-side tree builder and the HIP
+// library.  Not part of the ABI.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mra {
+
+enum FoldForm : int8_t { FOLD_FACTOR = 0, FOLD_GRAM = 1 };
+
+// Host-side description of the partition (Sec. 1.2) plus the execution plan
+// derived from it.  Regions are numbered in level order; the children of
+// region k at level m are J*k .. J*k+J-1 at level m+1, so every region's
+// observations are one contiguous range of the leaf-grouped order.
+struct HostTree {
+    int J = 4, M = 1, r = 1, nx = 1, ny = 1, rhat = 1, P = 16;
+    double offset = 0.0;
+    int64_t n_in = 0, n_nan = 0, n_elim = 0, n_used = 0;
+    int64_t nreg = 0, nleaf = 0;
+    std::vector<int64_t> lvl_start;  // M + 1 entries
+    std::vector<double> box;         // nreg * 4 (xlo, xhi, ylo, yhi)
+    std::vector<int64_t> obs_lo;     // nreg + 0: first observation of each region's subtree
+    std::vector<int64_t> obs_hi;     // one past the last
+    std::vector<double> x, y, z;     // used observations, grouped by leaf
+    std::vector<int64_t> orig;       // input index of each used observation
+};
+
+// Builds the partition on the host.  Returns an MRA_* status, message in err.
+int build_host_tree(const double* x, const double* y, const double* z, int64_t n, int J, int r,
+                    int M, double offset, const double* domain4, HostTree& t, std::string& err);
+
+}  // namespace mra

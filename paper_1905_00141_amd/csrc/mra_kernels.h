@@ -1,0 +1,56 @@
+// Device-side building blocks of the MRA hot path on gfx950.
+//
+// Notation (Sec. 1.1): levels m = 1 (root) .. M (finest); region R at level m
+// has ancestors A_1 .. A_m = R, knots Q_R (r_hat grid knots above the finest
+// level, the observations at the finest level).  The library works with the
+// whitened prior factors
+//     V^l(P) = C_l(P, Q_{A_l}) L_{A_l}^{-T},   L_R L_R^T = C_m(Q_R, Q_R),
+// for which the remainder recursion reads
+//     C_l(P, Q_{A_l}) = C(P, Q_{A_l}) - sum_{i<l} V^i(P) V^i(Q_{A_l})^T ,
+// and with factors F = L_S^{-1} [V | z] of the finest-level covariance
+//     S = C(S,S) - sum_l V^l V^l^T + tau I .
+// Tiles are padded from r_hat to P in {16, 32, 64}: padded knots carry zero
+// covariance with everything and an identity block in every factor.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mra {
+
+constexpr int NT = 256;  // threads per workgroup (4 wavefronts of 64)
+constexpr int TB = 64;   // output tile edge of the workgroup GEMM
+constexpr int KC = 16;   // K chunk staged through LDS
+constexpr int MAXL = 16; // maximum number of levels
+
+struct KArgs {
+    // tree (device)
+    const double* x;
+    const double* y;
+    const double* z;
+    const double* box;
+    const int64_t* obs_lo;
+    const int64_t* obs_hi;
+    const int64_t* vst_off;   // per region: offset of its V store (non-leaf), doubles
+    const int64_t* gram_off;  // per region: offset of its Gram matrix or -1
+    const int8_t* form;       // per region: FOLD_FACTOR / FOLD_GRAM
+    int64_t lvl[MAXL + 1];    // first level-order index of each level (0-based level)
+    int J, M, nx, ny, rhat, P, WF, WFs;
+    double offset;
+    int smooth;               // 0: exp(-t), 1: (1+t) exp(-t)
+    // per chunk of theta
+    const double* theta;      // ntheta x 3
+    int ntheta;
+    double* vst;   int64_t vst_stride;
+    double* F;     int64_t F_stride;
+    double* gram;  int64_t gram_stride;
+    double* dval;  int64_t d_stride;
+    double* scratch; int64_t scratch_stride;
+    int* status;              // per theta: 0, or 1 + global index of the failing region
+    const int* tasks;         // region list of this launch
+    int64_t ntasks;           // regions per theta
+    int level;                // level (1-based) of this launch
+    double* out;              // final: loglik per theta
+    double n_used;
+};
+
+}  // namespace mra

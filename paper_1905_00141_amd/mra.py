@@ -1,0 +1,163 @@
+"""Python binding of libmra.so: argument marshalling only.
+
+Every step of the likelihood runs in the library's HIP kernels.  Inputs may be
+NumPy arrays (host) or torch CUDA tensors (device, float64); PyTorch is used
+only for device memory and streams.  If the library is missing the import of
+this module fails: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmra.so")
+
+MRA_OK, MRA_EINVAL, MRA_ENOTPD, MRA_ENOMEM, MRA_EDEVICE, MRA_EDOMAIN = 0, -1, -2, -3, -4, -5
+MRA_EXP, MRA_MATERN = 0, 1
+MRA_DEVICE_PTRS = 1 << 0
+MRA_FOLD_GRAM = 1 << 4
+MRA_FOLD_FACTOR = 1 << 5
+
+EXPORTED = ["mra_build_tree", "mra_loglik", "mra_predict", "mra_free_tree", "mra_last_error",
+            "mra_tree_info", "mra_tree_arrays"]
+
+
+class MraInfo(C.Structure):
+    _fields_ = [("n_in", C.c_int64), ("n_nan", C.c_int64), ("n_elim", C.c_int64), ("n_used", C.c_int64),
+                ("J", C.c_int32), ("M", C.c_int32), ("r", C.c_int32), ("r_hat", C.c_int32), ("P", C.c_int32),
+                ("n_regions", C.c_int64), ("n_leaves", C.c_int64), ("leaf_min", C.c_int64),
+                ("leaf_max", C.c_int64), ("n_gram_regions", C.c_int64)]
+
+
+class MraError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libmra error {code}: {msg}")
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: run `python -m paper_1905_00141_amd.build` first")
+    L = C.CDLL(path)
+    vp, pd, i64 = C.c_void_p, C.c_void_p, C.c_int64
+    L.mra_build_tree.argtypes = [pd, pd, pd, i64, C.c_int, C.c_int, C.c_int, C.c_double, C.c_uint32, pd,
+                                 C.POINTER(vp)]
+    L.mra_build_tree.restype = C.c_int
+    L.mra_loglik.argtypes = [vp, C.c_int, C.c_double, pd, i64, pd, vp]
+    L.mra_loglik.restype = C.c_int
+    L.mra_predict.argtypes = [vp, C.c_int, C.c_double, pd, pd, pd, i64, pd, pd, vp]
+    L.mra_predict.restype = C.c_int
+    L.mra_free_tree.argtypes = [vp]
+    L.mra_free_tree.restype = None
+    L.mra_last_error.argtypes = []
+    L.mra_last_error.restype = C.c_char_p
+    L.mra_tree_info.argtypes = [vp, C.POINTER(MraInfo)]
+    L.mra_tree_info.restype = C.c_int
+    L.mra_tree_arrays.argtypes = [vp, pd, pd, pd, pd, pd]
+    L.mra_tree_arrays.restype = C.c_int
+    return L
+
+
+_lib = load_library()
+
+
+def _check(rc):
+    if rc != 0:
+        raise MraError(rc, _lib.mra_last_error().decode())
+
+
+def _ptr(a):
+    """Address of a contiguous float64 NumPy array or torch tensor."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags.c_contiguous and a.dtype == np.float64
+        return a.ctypes.data
+    assert a.is_contiguous() and str(a.dtype) == "torch.float64"
+    return a.data_ptr()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def family_code(family: str):
+    return {"exp": MRA_EXP, "matern": MRA_MATERN}[family]
+
+
+class Tree:
+    """Handle on a library-built MRA partition (mra_build_tree)."""
+
+    def __init__(self, x, y, z, J=4, r=16, M=3, offset=0.0, flags=0, domain=None):
+        dev = not isinstance(x, np.ndarray)
+        if not dev:
+            x = np.ascontiguousarray(x, dtype=np.float64)
+            y = np.ascontiguousarray(y, dtype=np.float64)
+            z = np.ascontiguousarray(z, dtype=np.float64)
+            n = len(x)
+        else:
+            n = x.numel()
+            flags |= MRA_DEVICE_PTRS
+        dom = None if domain is None else np.ascontiguousarray(domain, dtype=np.float64)
+        h = C.c_void_p()
+        _check(_lib.mra_build_tree(_ptr(x), _ptr(y), _ptr(z), n, J, r, M, float(offset), flags,
+                                   None if dom is None else dom.ctypes.data, C.byref(h)))
+        self._h = h
+        info = MraInfo()
+        _check(_lib.mra_tree_info(h, C.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in MraInfo._fields_}
+        self.n_used = info.n_used
+        self.M, self.J, self.r_hat, self.P = info.M, info.J, info.r_hat, info.P
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.mra_free_tree(h)
+            self._h = None
+
+    def arrays(self):
+        n, nl = self.info["n_used"], self.info["n_leaves"]
+        x, y, z = np.empty(n), np.empty(n), np.empty(n)
+        orig = np.empty(n, dtype=np.int64)
+        off = np.empty(nl + 1, dtype=np.int64)
+        _check(_lib.mra_tree_arrays(self._h, x.ctypes.data, y.ctypes.data, z.ctypes.data, orig.ctypes.data,
+                                    off.ctypes.data))
+        return dict(x=x, y=y, z=z, orig=orig, leaf_off=off)
+
+    def loglik(self, theta, family="matern", nu=0.5, out=None, stream=None):
+        """theta: (B, 3) NumPy array (host) or float64 CUDA tensor (device)."""
+        if isinstance(theta, np.ndarray) or not hasattr(theta, "data_ptr"):
+            th = np.ascontiguousarray(np.atleast_2d(theta), dtype=np.float64)
+            B = th.shape[0]
+            res = np.empty(B) if out is None else out
+        else:
+            th = theta
+            B = th.shape[0]
+            if out is None:
+                import torch
+                out = torch.empty(B, dtype=torch.float64, device=th.device)
+            res = out
+        _check(_lib.mra_loglik(self._h, family_code(family), float(nu), _ptr(th), B, _ptr(res),
+                               _stream_ptr(stream)))
+        return res
+
+    def predict(self, theta, px, py, family="matern", nu=0.5, stream=None):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        dev = not isinstance(px, np.ndarray)
+        if dev:
+            import torch
+            mean = torch.empty_like(px)
+            var = torch.empty_like(px)
+            th = torch.tensor(th, dtype=torch.float64, device=px.device)
+        else:
+            px = np.ascontiguousarray(px, dtype=np.float64)
+            py = np.ascontiguousarray(py, dtype=np.float64)
+            mean, var = np.empty(len(px)), np.empty(len(px))
+        _check(_lib.mra_predict(self._h, family_code(family), float(nu), _ptr(th), _ptr(px), _ptr(py), len(px),
+                                _ptr(mean), _ptr(var), _stream_ptr(stream)))
+        return mean, var
