@@ -1,0 +1,195 @@
+"""Benchmark of the MRA log-likelihood hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+A step is one mra_loglik call that evaluates the MRA log-likelihood of all
+covariance-parameter vectors of the batch (64 by default) over the whole tree:
+prior on every level, finest-level factors, folds to the root, final sums.
+Workload (BASELINE configuration "batched"): n = 2^20 locations from a seeded
+16-component Gaussian mixture on [0,1]^2, RFF Matern-3/2 values, M = 9, J = 4,
+r = 64, theta = 8 ranges (0.02..0.3) x 8 nuggets (1e-3..1e-1), FP64.
+Inputs (tree, theta) are resident in HBM before the timed region.
+
+Prints one JSON line (rank 0).  The kernel breakdown goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MRA loglik evals/s at n=2^20,r=64 (FP64 MFMA %); exact evals to MLE vs grid"
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 (vector and matrix), dense
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def canonical_flops(leaf_counts, J, M, p):
+    """Flops of the A/omega form of the recursion (prior + fold of every
+    non-empty region above the finest level, and every non-empty leaf)."""
+    import numpy as np
+    n = np.asarray(leaf_counts, dtype=np.float64)
+    L = M - 1
+    total = float(np.sum(2 * n * p * p * L * L + 2 * n * n * L * p + n ** 3 / 3))
+    counts = n
+    for m in range(M - 1, 0, -1):
+        counts = counts.reshape(-1, J).sum(axis=1)
+        total += float(np.count_nonzero(counts)) * 2 * p ** 3 * (m * (m - 1) + 1.0 / 3)
+    return total
+
+
+def cpu_baseline(cfg, theta, budget_s=25.0):
+    """The oracle, single-threaded, on whole subtrees of the same tree.  Evals/s
+    is extrapolated from the subtree's share of the canonical flops."""
+    import numpy as np
+    from oracle import oracle as o
+
+    fam = o.MATERN
+    t0 = time.time()
+    ot = o.Tree(cfg["x"], cfg["y"], cfg["z"], J=cfg["J"], r=cfg["r"], M=cfg["M"], domain=cfg["domain"])
+    build_s = time.time() - t0
+    off = ot.arrays()["leaf_off"]
+    counts = np.diff(off)
+    J, M, p = cfg["J"], cfg["M"], ot.rhat
+    full = canonical_flops(counts, J, M, p)
+    spent, done = 0.0, None
+    for level in range(min(6, M), 1, -1):
+        per = J ** (M - level)                      # leaves under one region of this level
+        sub = counts.reshape(-1, per).sum(axis=1)
+        target = counts.sum() / len(sub)
+        k = int(np.argmin(np.abs(sub - target)))    # a typical region of this level
+        f_sub = canonical_flops(counts[k * per:(k + 1) * per], J, M - level + 1, p)
+        t1 = time.time()
+        o.subtree_du(ot, theta, level, k, fam, cfg["nu"])
+        dt = time.time() - t1
+        spent += dt
+        done = dict(level=level, k=k, n_obs=int(sub[k]), seconds=dt, flops=f_sub)
+        log(f"[cpu_baseline] oracle subtree level {level} region {k}: {int(sub[k])} obs, {dt:.2f} s")
+        if dt >= 0.35 * budget_s or spent + 4.5 * dt > budget_s:
+            break
+    est = done["seconds"] * full / done["flops"]
+    return {
+        "value": 1.0 / est,
+        "unit": "evals/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one theta (alpha=1, range={theta[1]:.3g}, nugget={theta[2]:.3g}) on the subtree of "
+                   f"level-{done['level']} region {done['k']} ({done['n_obs']} of {int(counts.sum())} obs), "
+                   f"{done['seconds']:.2f} s single-threaded; scaled to the whole tree by canonical flops "
+                   f"({done['flops']:.3g} of {full:.3g}); oracle tree build {build_s:.1f} s not counted"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-theta", type=int, default=64, help="must be a square (ranges x nuggets)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--scale", type=int, default=0, help="shrink n by 4^scale and M by scale (quick runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(this build runs on a single MI355X; see DESIGN.md for the sharding design)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    from paper_1905_00141_amd import mra, synth
+
+    nt = int(round(math.sqrt(args.n_theta)))
+    n = (1 << 20) >> (2 * args.scale)
+    M = 9 - args.scale
+    t0 = time.time()
+    cfg = synth.config3(device="cuda", n=n, M=M, n_theta=(nt, nt))
+    log(f"[bench] data {cfg['name']} generated in {time.time() - t0:.1f} s")
+    t0 = time.time()
+    tree = mra.Tree(cfg["x"], cfg["y"], cfg["z"], J=cfg["J"], r=cfg["r"], M=cfg["M"], domain=cfg["domain"])
+    info = tree.info
+    log(f"[bench] tree built in {time.time() - t0:.1f} s: n_used {info['n_used']}, leaves "
+        f"{info['leaf_min']}..{info['leaf_max']} obs, {info['n_gram_regions']} Gram-form regions")
+    theta = torch.tensor(cfg["theta"], dtype=torch.float64, device=dev)
+    B = theta.shape[0]
+    out = torch.empty(B, dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+
+    for i in range(args.warmup):
+        t1 = time.time()
+        tree.loglik(theta, cfg["family"], cfg["nu"], out=out, stream=stream)
+        stream.synchronize()
+        log(f"[bench] warmup step {i} {time.time() - t1:.3f} s")
+    ll = out.cpu().numpy()
+    assert np.all(np.isfinite(ll)), ll
+
+    mra.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        tree.loglik(theta, cfg["family"], cfg["nu"], out=out, stream=stream)
+        stream.synchronize()
+        log(f"[bench] step {i} done at {time.perf_counter() - t0:.3f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    mra.profile_enable(False)
+    stats = mra.profile_read()
+    ms_step = 1000.0 * elapsed / args.steps
+    value = B * args.steps / elapsed
+
+    tot_ms = sum(s["ms"] for s in stats)
+    for s in sorted(stats, key=lambda s: -s["ms"]):
+        tf = s["flops"] / (s["ms"] * 1e-3) / 1e12 if s["ms"] > 0 else 0.0
+        log(f"[bench] {s['name']:14s} L{s['level']:<2d} launches {s['launches']:4d} "
+            f"{s['ms'] / args.steps:10.3f} ms/step {100 * s['ms'] / max(tot_ms, 1e-9):5.1f}%  {tf:7.3f} TF/s")
+    dom = max(stats, key=lambda s: s["ms"])
+    ach = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+    roof = {
+        "bound": "alu",
+        "kernel": f"{dom['name']} level {dom['level']}",
+        "achieved": ach,
+        "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": ach / FP64_PEAK_TFLOPS,
+        "traffic": None,
+        "share_of_step": dom["ms"] / max(tot_ms, 1e-9),
+    }
+    all_flops = sum(s["flops"] for s in stats)
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": cfg["name"], "n": int(n), "n_used": int(info["n_used"]), "M": M, "J": 4, "r": 64,
+            "r_hat": int(info["r_hat"]), "n_theta": int(B), "family": "matern", "nu": 1.5,
+            "leaf_obs_min": int(info["leaf_min"]), "leaf_obs_max": int(info["leaf_max"]),
+            "whole_path_tflops": all_flops / elapsed / 1e12,
+        },
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(cfg, cfg["theta"][0])
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

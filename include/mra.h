@@ -135,6 +135,26 @@ int mra_tree_info(const mra_tree *tree, mra_info *info);
 int mra_tree_arrays(const mra_tree *tree, double *x, double *y, double *z, int64_t *orig,
                     int64_t *leaf_off);
 
+/*
+ * Optional per-launch timing, for measurement.  While enabled, every kernel
+ * launch of mra_loglik is bracketed by HIP events on the caller's stream.
+ * mra_profile_read waits for the recorded events, aggregates them by kernel
+ * and level (elapsed milliseconds, launch count, and the algorithmic FP64
+ * flops of what those launches computed, padding excluded), writes up to
+ * cap entries, sets *count to the number of entries and clears the record.
+ * Process-wide; not meant to be toggled while other threads run mra_loglik.
+ */
+typedef struct mra_kernel_stat {
+    char name[32];
+    int32_t level;
+    int64_t launches;
+    double ms;
+    double flops;
+} mra_kernel_stat;
+
+int mra_profile_enable(int on);
+int mra_profile_read(mra_kernel_stat *out, int cap, int *count);
+
 #ifdef __cplusplus
 }
 #endif

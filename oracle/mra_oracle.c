@@ -410,6 +410,53 @@ static void prior_rows(rctx *ctx, int np, const double *px, const double *py, in
     }
 }
 
+/* Prior of the knots of non-leaf region k at level m: B^l_R for l = 1..m and
+ * the Cholesky factor of B^m_R, stored as ctx->anc[m] (its ancestors must be
+ * in ctx->anc[1..m-1]). */
+static void prior_region(rctx *ctx, int m, int64_t k) {
+    const otree *t = ctx->t;
+    int p = ctx->p;
+    anc_t *me = &ctx->anc[m];
+    const double *bx = t->box + 4 * (t->lvl_start[m - 1] + k);
+    me->kx = malloc(sizeof(double) * p);
+    me->ky = malloc(sizeof(double) * p);
+    oracle_box_knots(bx[0], bx[1], bx[2], bx[3], t->r, t->offset, me->kx, me->ky);
+    double *Z[O_MAXLEV + 1] = {0};
+    for (int l = 1; l <= m; l++) {
+        me->B[l] = malloc(sizeof(double) * p * p);
+        Z[l] = (l < m) ? malloc(sizeof(double) * p * p) : NULL;
+    }
+    /* B^l_R for l < m (ancestors strictly above), then B^m_R from R's own B^i */
+    me->L = NULL;
+    prior_rows(ctx, p, me->kx, me->ky, m - 1, me->B, Z);
+    {
+        double *Bm = me->B[m];
+        for (int a = 0; a < p; a++)
+            for (int b = 0; b < p; b++) {
+                double s = cov(me->kx[a], me->ky[a], me->kx[b], me->ky[b], &ctx->c);
+                for (int i = 1; i < m; i++)
+                    for (int kk = 0; kk < p; kk++) s -= Z[i][(int64_t)a * p + kk] * me->B[i][(int64_t)b * p + kk];
+                Bm[(int64_t)a * p + b] = s;
+            }
+        for (int a = 0; a < p; a++)
+            for (int b = 0; b < a; b++) {
+                double v = 0.5 * (Bm[(int64_t)a * p + b] + Bm[(int64_t)b * p + a]);
+                Bm[(int64_t)a * p + b] = Bm[(int64_t)b * p + a] = v;
+            }
+        me->L = malloc(sizeof(double) * p * p);
+        memcpy(me->L, Bm, sizeof(double) * p * p);
+        if (chol(me->L, p)) { ctx->status = O_ENOTPD; ctx->bad_region = t->lvl_start[m - 1] + k; }
+    }
+    for (int l = 1; l < m; l++) free(Z[l]);
+}
+
+static void free_region(rctx *ctx, int m) {
+    anc_t *me = &ctx->anc[m];
+    for (int l = 1; l <= m; l++) free(me->B[l]);
+    free(me->L); free(me->kx); free(me->ky);
+    memset(me, 0, sizeof *me);
+}
+
 /* Visit region k at level m (1-based).  On return, A (size (m-1)p square,
  * full), w ((m-1)p) hold the region's statistics for its ancestors 1..m-1, and
  * *du the sum of d+u over the subtree. */
@@ -486,37 +533,7 @@ static void visit(rctx *ctx, int m, int64_t k, double *A, double *w, double *du)
 
     /* non-leaf region at level m: prior (knots), children, fold */
     anc_t *me = &ctx->anc[m];
-    const double *bx = t->box + 4 * (t->lvl_start[m - 1] + k);
-    me->kx = malloc(sizeof(double) * p);
-    me->ky = malloc(sizeof(double) * p);
-    oracle_box_knots(bx[0], bx[1], bx[2], bx[3], t->r, t->offset, me->kx, me->ky);
-    double *Z[O_MAXLEV + 1] = {0};
-    for (int l = 1; l <= m; l++) {
-        me->B[l] = malloc(sizeof(double) * p * p);
-        Z[l] = (l < m) ? malloc(sizeof(double) * p * p) : NULL;
-    }
-    /* B^l_R for l < m (ancestors strictly above), then B^m_R from R's own B^i */
-    me->L = NULL;
-    prior_rows(ctx, p, me->kx, me->ky, m - 1, me->B, Z);
-    {
-        double *Bm = me->B[m];
-        for (int a = 0; a < p; a++)
-            for (int b = 0; b < p; b++) {
-                double s = cov(me->kx[a], me->ky[a], me->kx[b], me->ky[b], &ctx->c);
-                for (int i = 1; i < m; i++)
-                    for (int kk = 0; kk < p; kk++) s -= Z[i][(int64_t)a * p + kk] * me->B[i][(int64_t)b * p + kk];
-                Bm[(int64_t)a * p + b] = s;
-            }
-        for (int a = 0; a < p; a++)
-            for (int b = 0; b < a; b++) {
-                double v = 0.5 * (Bm[(int64_t)a * p + b] + Bm[(int64_t)b * p + a]);
-                Bm[(int64_t)a * p + b] = Bm[(int64_t)b * p + a] = v;
-            }
-        me->L = malloc(sizeof(double) * p * p);
-        memcpy(me->L, Bm, sizeof(double) * p * p);
-        if (chol(me->L, p)) { ctx->status = O_ENOTPD; ctx->bad_region = t->lvl_start[m - 1] + k; }
-    }
-    for (int l = 1; l < m; l++) free(Z[l]);
+    prior_region(ctx, m, k);
     int q = m * p;
     double *At = calloc((size_t)q * q, sizeof(double));
     double *wt = calloc((size_t)q, sizeof(double));
@@ -575,9 +592,37 @@ static void visit(rctx *ctx, int m, int64_t k, double *A, double *w, double *du)
         free(Ki);
     }
     free(At); free(wt);
-    for (int l = 1; l <= m; l++) free(me->B[l]);
-    free(me->L); free(me->kx); free(me->ky);
-    memset(me, 0, sizeof *me);
+    free_region(ctx, m);
+}
+
+/* Sum of d + u over the subtree of region k at level `level` for one theta
+ * (the ancestors' priors are computed first).  A bounded piece of a full
+ * evaluation, used to time the oracle on large workloads. */
+int oracle_mra_subtree(const otree *t, int family, double nu, const double *theta, int level, int64_t k,
+                       double *du_out) {
+    if (level < 1 || level > t->M) return fail(O_EINVAL, "bad level");
+    rctx *ctx = calloc(1, sizeof *ctx);
+    ctx->t = t;
+    ctx->p = t->rhat;
+    int rc = make_par(family, nu, theta, &ctx->c);
+    if (rc) { free(ctx); return rc; }
+    for (int l = 1; l < level; l++) {
+        int64_t kl = k;
+        for (int e = 0; e < level - l; e++) kl /= t->J;
+        prior_region(ctx, l, kl);
+    }
+    int q = (level - 1) * ctx->p;
+    double *A = malloc(sizeof(double) * (size_t)(q > 0 ? q * q : 1));
+    double *w = malloc(sizeof(double) * (size_t)(q > 0 ? q : 1));
+    double du = 0.0;
+    visit(ctx, level, k, A, w, &du);
+    for (int l = 1; l < level; l++) free_region(ctx, l);
+    free(A); free(w);
+    int st = ctx->status;
+    free(ctx);
+    if (st) return fail(O_ENOTPD, "not positive definite in subtree");
+    *du_out = du;
+    return O_OK;
 }
 
 static const double LOG2PI = 1.8378770664093454835606594728112;

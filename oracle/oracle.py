@@ -164,3 +164,16 @@ class Tree:
         f = lib().oracle_dense_predict if dense else lib().oracle_mra_predict
         _check(f(self._h, family, float(nu), _p(th), _p(px), _p(py), len(px), _p(mean), _p(var)))
         return mean, var
+
+
+def subtree_du(tree: Tree, theta, level: int, k: int, family=MATERN, nu=0.5) -> float:
+    """Sum of d + u over one subtree (bounded piece of an evaluation, for timing)."""
+    L = lib()
+    if not hasattr(L, "_subtree_typed"):
+        L.oracle_mra_subtree.argtypes = [C.c_void_p, C.c_int, C.c_double, C.POINTER(C.c_double), C.c_int,
+                                         C.c_int64, C.POINTER(C.c_double)]
+        L._subtree_typed = True
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = C.c_double()
+    _check(L.oracle_mra_subtree(tree._h, family, float(nu), _p(th), level, k, C.byref(out)))
+    return out.value

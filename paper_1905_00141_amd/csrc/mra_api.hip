@@ -5,7 +5,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -85,6 +87,9 @@ struct mra_tree {
     int64_t scratch_leaf = 0, scratch_fold = 0;  // doubles per workgroup slot
     int root_gram = 0;
     int64_t n_gram = 0, leaf_min = 0, leaf_max = 0;
+    // algorithmic FP64 flops of one theta, per launch kind and level
+    std::vector<double> fl_prior, fl_factor, fl_gram;
+    double fl_leaf = 0.0;
 
     ~mra_tree() {
         void* ps[] = {d_x, d_y, d_z, d_box, d_obs_lo, d_obs_hi, d_vst_off, d_gram_off, d_form, d_leaf};
@@ -93,6 +98,116 @@ struct mra_tree {
             for (int* p : *v) if (p) (void)hipFree(p);
     }
 };
+
+// Algorithmic FP64 flop counts of what each launch computes for one theta,
+// with p = r_hat (padding excluded), n = observations of a region:
+//   prior, level m   : p^3 [ m (m-1) + 1/3 ]   (m-1 chained GEMM + TRSM steps,
+//                      the Schur SYRK and a p x p Cholesky)
+//   leaf, L = M-1    : n p^2 L^2 + L n^2 p + n^3/3 + n^2 (L p + 1)
+//   factor fold, m   : n^2 p + n^3/3 + n^2 ((m-1) p + 1)
+//   Gram fold, m     : sum_children n_c D^2 + p^3/3 + (D-p) p^2 + (D-p)^2 p,
+//                      D = m p + 1 (Gram-form children: D^2/2 additions)
+static void plan_flops(mra_tree& t) {
+    const HostTree& h = t.h;
+    const int M = h.M;
+    const double p = h.rhat;
+    t.fl_prior.assign(M, 0.0);
+    t.fl_factor.assign(M, 0.0);
+    t.fl_gram.assign(M, 0.0);
+    for (int m = 1; m < M; ++m) {
+        t.fl_prior[m] = double(t.prior_tasks[m].size()) * p * p * p * (double(m) * (m - 1) + 1.0 / 3.0);
+        for (int g : t.factor_tasks[m]) {
+            const double n = double(h.obs_hi[g] - h.obs_lo[g]);
+            t.fl_factor[m] += n * n * p + n * n * n / 3.0 + n * n * ((m - 1) * p + 1);
+        }
+        const double D = m * p + 1;
+        for (int g : t.gram_tasks[m]) {
+            const int64_t k = g - h.lvl_start[m - 1];
+            double f = p * p * p / 3.0 + (D - p) * p * p + (D - p) * (D - p) * p;
+            for (int j = 0; j < h.J; ++j) {
+                const int64_t gc = h.lvl_start[m] + h.J * k + j;
+                const double nc = double(h.obs_hi[gc] - h.obs_lo[gc]);
+                if (m + 1 == M || t.form[gc] == FOLD_FACTOR) f += nc * D * D;
+                else f += D * D / 2;
+            }
+            t.fl_gram[m] += f;
+        }
+    }
+    const double L = M - 1;
+    t.fl_leaf = 0.0;
+    for (int g : t.leaf_tasks) {
+        const double n = double(h.obs_hi[g] - h.obs_lo[g]);
+        t.fl_leaf += n * p * p * L * L + L * n * n * p + n * n * n / 3.0 + n * n * (L * p + 1);
+    }
+}
+
+// ---- optional per-launch timing (HIP events around every launch) ----------
+namespace {
+struct ProfRec {
+    int kind, level;
+    hipEvent_t a, b;
+    double flops;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+const char* const KIND_NAMES[] = {"k_prior", "k_leaf", "k_fold_factor", "k_fold_gram", "k_final"};
+}  // namespace
+
+template <class F>
+static hipError_t timed(int kind, int level, double flops, hipStream_t st, F&& launch) {
+    bool on;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        on = g_prof_on;
+    }
+    if (!on) return launch();
+    ProfRec r{kind, level, nullptr, nullptr, flops};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return launch();
+    (void)hipEventRecord(r.a, st);
+    const hipError_t e = launch();
+    (void)hipEventRecord(r.b, st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back(r);
+    return e;
+}
+
+extern "C" int mra_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return MRA_OK;
+}
+
+extern "C" int mra_profile_read(mra_kernel_stat* out, int cap, int* count) {
+    if (!count) return fail(MRA_EINVAL, "count is NULL");
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        recs.swap(g_prof);
+    }
+    std::vector<mra_kernel_stat> agg;
+    for (ProfRec& r : recs) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess) (void)hipEventElapsedTime(&ms, r.a, r.b);
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+        mra_kernel_stat* s = nullptr;
+        for (auto& x : agg)
+            if (x.level == r.level && std::strcmp(x.name, KIND_NAMES[r.kind]) == 0) s = &x;
+        if (!s) {
+            agg.push_back(mra_kernel_stat{});
+            s = &agg.back();
+            std::snprintf(s->name, sizeof s->name, "%s", KIND_NAMES[r.kind]);
+            s->level = r.level;
+        }
+        s->launches += 1;
+        s->ms += ms;
+        s->flops += r.flops;
+    }
+    *count = int(agg.size());
+    for (int i = 0; i < int(agg.size()) && i < cap; ++i) out[i] = agg[i];
+    return MRA_OK;
+}
 
 extern "C" const char* mra_last_error(void) { return g_err.c_str(); }
 
@@ -187,6 +302,7 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
     t->WF = (M - 1) * P + 1;
     t->WFs = (t->WF + 3) & ~3;
     t->root_gram = (M > 1 && t->form[0] == FOLD_GRAM) ? 1 : 0;
+    plan_flops(*t);
 
     // device copies
     std::vector<int64_t> lo(h.obs_lo), hi(h.obs_hi);
@@ -340,22 +456,25 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
             a.ntasks = int64_t(t->prior_tasks[m].size());
             if (a.ntasks == 0) continue;
             const int64_t tot = a.ntasks * nb;
-            HIPCHK(launch_prior(a, int(std::min<int64_t>(tot, 1 << 16)), st));
+            HIPCHK(timed(0, m, t->fl_prior[m] * nb, st, [&] { return launch_prior(a, int(std::min<int64_t>(tot, 1 << 16)), st); }));
         }
         a.level = M;
         a.tasks = t->d_leaf;
         a.ntasks = int64_t(t->leaf_tasks.size());
-        if (a.ntasks > 0) HIPCHK(launch_leaf(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st));
+        if (a.ntasks > 0)
+            HIPCHK(timed(1, M, t->fl_leaf * nb, st, [&] { return launch_leaf(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st); }));
         for (int m = M - 1; m >= 1; --m) {
             a.level = m;
             a.tasks = t->d_factor[m];
             a.ntasks = int64_t(t->factor_tasks[m].size());
-            if (a.ntasks > 0) HIPCHK(launch_fold_factor(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st));
+            if (a.ntasks > 0)
+                HIPCHK(timed(2, m, t->fl_factor[m] * nb, st, [&] { return launch_fold_factor(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st); }));
             a.tasks = t->d_gramt[m];
             a.ntasks = int64_t(t->gram_tasks[m].size());
-            if (a.ntasks > 0) HIPCHK(launch_fold_gram(a, int(std::min<int64_t>(a.ntasks * nb, 1 << 16)), st));
+            if (a.ntasks > 0)
+                HIPCHK(timed(3, m, t->fl_gram[m] * nb, st, [&] { return launch_fold_gram(a, int(std::min<int64_t>(a.ntasks * nb, 1 << 16)), st); }));
         }
-        HIPCHK(launch_final(a, h.nreg, t->root_gram, st));
+        HIPCHK(timed(4, 0, 0.0, st, [&] { return launch_final(a, h.nreg, t->root_gram, st); }));
     }
     if (!dev) {
         HIPCHK(hipMemcpyAsync(loglik, d_out, B * 8, hipMemcpyDeviceToHost, st));

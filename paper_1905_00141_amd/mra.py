@@ -22,7 +22,7 @@ MRA_FOLD_GRAM = 1 << 4
 MRA_FOLD_FACTOR = 1 << 5
 
 EXPORTED = ["mra_build_tree", "mra_loglik", "mra_predict", "mra_free_tree", "mra_last_error",
-            "mra_tree_info", "mra_tree_arrays"]
+            "mra_tree_info", "mra_tree_arrays", "mra_profile_enable", "mra_profile_read"]
 
 
 class MraInfo(C.Structure):
@@ -30,6 +30,11 @@ class MraInfo(C.Structure):
                 ("J", C.c_int32), ("M", C.c_int32), ("r", C.c_int32), ("r_hat", C.c_int32), ("P", C.c_int32),
                 ("n_regions", C.c_int64), ("n_leaves", C.c_int64), ("leaf_min", C.c_int64),
                 ("leaf_max", C.c_int64), ("n_gram_regions", C.c_int64)]
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("level", C.c_int32), ("launches", C.c_int64), ("ms", C.c_double),
+                ("flops", C.c_double)]
 
 
 class MraError(RuntimeError):
@@ -58,6 +63,10 @@ def load_library(path: str = LIB_PATH):
     L.mra_tree_info.restype = C.c_int
     L.mra_tree_arrays.argtypes = [vp, pd, pd, pd, pd, pd]
     L.mra_tree_arrays.restype = C.c_int
+    L.mra_profile_enable.argtypes = [C.c_int]
+    L.mra_profile_enable.restype = C.c_int
+    L.mra_profile_read.argtypes = [C.POINTER(KernelStat), C.c_int, C.POINTER(C.c_int)]
+    L.mra_profile_read.restype = C.c_int
     return L
 
 
@@ -84,6 +93,20 @@ def _stream_ptr(stream):
     if stream is None:
         return None
     return int(getattr(stream, "cuda_stream", stream))
+
+
+def profile_enable(on: bool = True):
+    _check(_lib.mra_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """Per (kernel, level): launches, total ms, algorithmic flops since the last read."""
+    cap = 256
+    buf = (KernelStat * cap)()
+    cnt = C.c_int()
+    _check(_lib.mra_profile_read(buf, cap, C.byref(cnt)))
+    return [dict(name=buf[i].name.decode(), level=buf[i].level, launches=buf[i].launches, ms=buf[i].ms,
+                 flops=buf[i].flops) for i in range(min(cnt.value, cap))]
 
 
 def family_code(family: str):
