@@ -16,8 +16,11 @@
 #include "mra_kernels.h"
 
 namespace mra {
-hipError_t launch_prior(const KArgs& a, int grid, hipStream_t st);
+int chain_lmax(int P);
+hipError_t launch_chain(const KArgs& a, int mode, int grid, hipStream_t st);
+hipError_t launch_prior_finish(const KArgs& a, int grid, hipStream_t st);
 hipError_t launch_leaf(const KArgs& a, int grid, hipStream_t st);
+hipError_t launch_leaf_small(const KArgs& a, int grid, hipStream_t st);
 hipError_t launch_fold_factor(const KArgs& a, int grid, hipStream_t st);
 hipError_t launch_fold_gram(const KArgs& a, int grid, hipStream_t st);
 hipError_t launch_final(const KArgs& a, int64_t nreg, int root_gram, hipStream_t st);
@@ -81,18 +84,21 @@ struct mra_tree {
     int64_t vst_size = 0, gram_size = 0;
     int WF = 1, WFs = 2;
     std::vector<std::vector<int>> prior_tasks, factor_tasks, gram_tasks;  // index by level (1..M-1)
-    std::vector<int> leaf_tasks;
+    std::vector<int> leaf_tasks, small_tasks;  // leaves with > 16 / <= 16 observations
     std::vector<int*> d_prior, d_factor, d_gramt;
     int* d_leaf = nullptr;
+    int* d_small = nullptr;
     int64_t scratch_leaf = 0, scratch_fold = 0;  // doubles per workgroup slot
     int root_gram = 0;
     int64_t n_gram = 0, leaf_min = 0, leaf_max = 0;
     // algorithmic FP64 flops of one theta, per launch kind and level
-    std::vector<double> fl_prior, fl_factor, fl_gram;
-    double fl_leaf = 0.0;
+    std::vector<double> fl_chain, fl_pfin, fl_factor, fl_gram;
+    double fl_leaf = 0.0, fl_small = 0.0;
+    void* ws = nullptr;  // Workspace*, owned
 
-    ~mra_tree() {
-        void* ps[] = {d_x, d_y, d_z, d_box, d_obs_lo, d_obs_hi, d_vst_off, d_gram_off, d_form, d_leaf};
+    ~mra_tree();
+    void free_device() {
+        void* ps[] = {d_x, d_y, d_z, d_box, d_obs_lo, d_obs_hi, d_vst_off, d_gram_off, d_form, d_leaf, d_small};
         for (void* p : ps) if (p) (void)hipFree(p);
         for (auto* v : {&d_prior, &d_factor, &d_gramt})
             for (int* p : *v) if (p) (void)hipFree(p);
@@ -101,21 +107,27 @@ struct mra_tree {
 
 // Algorithmic FP64 flop counts of what each launch computes for one theta,
 // with p = r_hat (padding excluded), n = observations of a region:
-//   prior, level m   : p^3 [ m (m-1) + 1/3 ]   (m-1 chained GEMM + TRSM steps,
-//                      the Schur SYRK and a p x p Cholesky)
-//   leaf, L = M-1    : n p^2 L^2 + L n^2 p + n^3/3 + n^2 (L p + 1)
-//   factor fold, m   : n^2 p + n^3/3 + n^2 ((m-1) p + 1)
-//   Gram fold, m     : sum_children n_c D^2 + p^3/3 + (D-p) p^2 + (D-p)^2 p,
-//                      D = m p + 1 (Gram-form children: D^2/2 additions)
+//   chain, level m knots : r_hat p^2 (m-1)^2  (per ancestor level l: the
+//                          2 p^2 (l-1) product with earlier blocks and the
+//                          p^2 triangular product with L_{A_l}^{-1})
+//   chain, observations  : n p^2 (M-1)^2 summed over level-(M-1) regions
+//   prior finish, m      : (m-1) p^3 + p^3/3 + p^3/3 (SYRK, Cholesky, inverse)
+//   leaf finish          : (M-1) n^2 p + n^3/3 + n^2 ((M-1) p + 1)
+//   factor fold, m       : n^2 p + n^3/3 + n^2 ((m-1) p + 1)
+//   Gram fold, m         : sum_children n_c D^2 + p^3/3 + (D-p) p^2 + (D-p)^2 p,
+//                          D = m p + 1 (Gram-form children: D^2/2 additions)
 static void plan_flops(mra_tree& t) {
     const HostTree& h = t.h;
     const int M = h.M;
     const double p = h.rhat;
-    t.fl_prior.assign(M, 0.0);
+    t.fl_chain.assign(M + 1, 0.0);
+    t.fl_pfin.assign(M, 0.0);
     t.fl_factor.assign(M, 0.0);
     t.fl_gram.assign(M, 0.0);
     for (int m = 1; m < M; ++m) {
-        t.fl_prior[m] = double(t.prior_tasks[m].size()) * p * p * p * (double(m) * (m - 1) + 1.0 / 3.0);
+        const double nr = double(t.prior_tasks[m].size());
+        t.fl_chain[m] = nr * p * p * p * double(m - 1) * (m - 1);
+        t.fl_pfin[m] = nr * p * p * p * (double(m - 1) + 2.0 / 3.0);
         for (int g : t.factor_tasks[m]) {
             const double n = double(h.obs_hi[g] - h.obs_lo[g]);
             t.fl_factor[m] += n * n * p + n * n * n / 3.0 + n * n * ((m - 1) * p + 1);
@@ -134,10 +146,15 @@ static void plan_flops(mra_tree& t) {
         }
     }
     const double L = M - 1;
-    t.fl_leaf = 0.0;
+    t.fl_chain[M] = double(h.n_used) * p * p * L * L;
+    t.fl_leaf = t.fl_small = 0.0;
     for (int g : t.leaf_tasks) {
         const double n = double(h.obs_hi[g] - h.obs_lo[g]);
-        t.fl_leaf += n * p * p * L * L + L * n * n * p + n * n * n / 3.0 + n * n * (L * p + 1);
+        t.fl_leaf += L * n * n * p + n * n * n / 3.0 + n * n * (L * p + 1);
+    }
+    for (int g : t.small_tasks) {
+        const double n = double(h.obs_hi[g] - h.obs_lo[g]);
+        t.fl_small += L * n * n * p + n * n * n / 3.0 + n * n * (L * p + 1);
     }
 }
 
@@ -151,7 +168,8 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
-const char* const KIND_NAMES[] = {"k_prior", "k_leaf", "k_fold_factor", "k_fold_gram", "k_final"};
+const char* const KIND_NAMES[] = {"k_chain", "k_prior_finish", "k_leaf_finish", "k_fold_factor", "k_fold_gram",
+                                  "k_final", "k_leaf_small"};
 }  // namespace
 
 template <class F>
@@ -253,6 +271,11 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
     if (rc) { delete t; return fail(rc, err); }
     const HostTree& h = t->h;
     const int P = h.P;
+    if (M - 1 > chain_lmax(P)) {
+        delete t;
+        return fail(MRA_EINVAL, "M - 1 = " + std::to_string(M - 1) + " exceeds " + std::to_string(chain_lmax(P)) +
+                                    " levels above the finest for r_hat padded to " + std::to_string(P));
+    }
 
     // plan: fold form of every non-leaf region, storage offsets, task lists
     t->form.assign(h.nreg, FOLD_FACTOR);
@@ -276,7 +299,7 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
             if (np <= thr) {
                 t->form[g] = FOLD_FACTOR;
                 t->factor_tasks[m].push_back(int(g));
-                t->scratch_fold = std::max(t->scratch_fold, np * np);
+                if (np > 64) t->scratch_fold = std::max(t->scratch_fold, np * np);
             } else {
                 t->form[g] = FOLD_GRAM;
                 t->gram_tasks[m].push_back(int(g));
@@ -293,9 +316,11 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
         const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
         t->leaf_min = std::min(t->leaf_min, nc);
         t->leaf_max = std::max(t->leaf_max, nc);
-        if (nc > 0) {
+        if (nc > 16) {
             t->leaf_tasks.push_back(int(g));
-            t->scratch_leaf = std::max(t->scratch_leaf, nc * nc);
+            if (nc > 64) t->scratch_leaf = std::max(t->scratch_leaf, nc * nc);
+        } else if (nc > 0) {
+            t->small_tasks.push_back(int(g));
         }
     }
     if (t->leaf_min == INT64_MAX) t->leaf_min = 0;
@@ -309,7 +334,8 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
     if ((rc = upload(&t->d_x, h.x)) || (rc = upload(&t->d_y, h.y)) || (rc = upload(&t->d_z, h.z)) ||
         (rc = upload(&t->d_box, h.box)) || (rc = upload(&t->d_obs_lo, lo)) || (rc = upload(&t->d_obs_hi, hi)) ||
         (rc = upload(&t->d_vst_off, t->vst_off)) || (rc = upload(&t->d_gram_off, t->gram_off)) ||
-        (rc = upload(&t->d_form, t->form)) || (rc = upload(&t->d_leaf, t->leaf_tasks))) {
+        (rc = upload(&t->d_form, t->form)) || (rc = upload(&t->d_leaf, t->leaf_tasks)) ||
+        (rc = upload(&t->d_small, t->small_tasks))) {
         delete t;
         return fail(rc, "device allocation or copy failed while uploading the tree");
     }
@@ -372,6 +398,77 @@ static int region_level(const HostTree& h, int64_t g) {
         if (e_ != hipSuccess) { rc = fail(MRA_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); goto done; } \
     } while (0)
 
+// Device workspace of a tree, kept between calls (allocation of the large
+// buffers is not repeated per evaluation).  Calls on one tree are serialised:
+// a call on a different stream first waits for the previous call's work.
+struct Workspace {
+    double *vst = nullptr, *F = nullptr, *gram = nullptr, *dval = nullptr, *scratch = nullptr;
+    double *th = nullptr, *out = nullptr;
+    int* status = nullptr;
+    int64_t Bc = 0, nslot = 0, scratch_per = 0, cap_B = 0;
+    hipEvent_t done = nullptr;
+    hipStream_t last = nullptr;
+    bool used = false;
+    void release() {
+        if (done) { (void)hipEventSynchronize(done); (void)hipEventDestroy(done); done = nullptr; }
+        for (void* p : {static_cast<void*>(vst), static_cast<void*>(F), static_cast<void*>(gram),
+                        static_cast<void*>(dval), static_cast<void*>(scratch), static_cast<void*>(th),
+                        static_cast<void*>(out), static_cast<void*>(status)})
+            if (p) (void)hipFree(p);
+        vst = F = gram = dval = scratch = th = out = nullptr;
+        status = nullptr;
+        Bc = nslot = cap_B = 0;
+        used = false;
+    }
+};
+
+static std::mutex g_ws_mu;
+
+static Workspace& workspace_of(const mra_tree* t);
+
+static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStream_t st) {
+    const HostTree& h = t->h;
+    const int64_t F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
+    const int64_t per_theta = t->vst_size + F_stride + t->gram_size + h.nreg;
+    const int64_t scratch_per = std::max<int64_t>({t->scratch_leaf, t->scratch_fold, 1});
+    if (w.Bc > 0 && (w.Bc >= B || w.Bc >= 64) && w.cap_B >= B) return MRA_OK;
+    if (w.Bc > 0) {
+        // grow: wait for the last user, release, reallocate
+        w.release();
+    }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(MRA_EDEVICE, "hipMemGetInfo failed");
+    const double budget = 0.6 * double(free_b) / 8.0;  // doubles
+    const int64_t nslot = std::min<int64_t>(2048, std::max<int64_t>(1, int64_t(0.2 * budget / double(scratch_per))));
+    const double left = budget - double(nslot) * double(scratch_per);
+    const int64_t Bc = std::min<int64_t>(std::max<int64_t>(B, 1), int64_t(left / double(per_theta)));
+    if (Bc < 1) return fail(MRA_ENOMEM, "not enough device memory for one theta");
+    const int64_t capB = std::max<int64_t>(B, 64);
+    auto al = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 8)) == hipSuccess; };
+    if (!al(reinterpret_cast<void**>(&w.vst), size_t(Bc) * t->vst_size * 8) ||
+        !al(reinterpret_cast<void**>(&w.F), size_t(Bc) * F_stride * 8) ||
+        !al(reinterpret_cast<void**>(&w.gram), size_t(Bc) * t->gram_size * 8) ||
+        !al(reinterpret_cast<void**>(&w.dval), size_t(Bc) * h.nreg * 8) ||
+        !al(reinterpret_cast<void**>(&w.scratch), size_t(nslot) * scratch_per * 8) ||
+        !al(reinterpret_cast<void**>(&w.status), size_t(capB) * sizeof(int)) ||
+        !al(reinterpret_cast<void**>(&w.th), size_t(capB) * 3 * 8) ||
+        !al(reinterpret_cast<void**>(&w.out), size_t(capB) * 8)) {
+        (void)hipGetLastError();
+        w.release();
+        return fail(MRA_ENOMEM, "device allocation of the evaluation workspace failed");
+    }
+    if (hipEventCreateWithFlags(&w.done, hipEventDisableTiming) != hipSuccess) {
+        w.release();
+        return fail(MRA_EDEVICE, "hipEventCreate failed");
+    }
+    w.Bc = Bc;
+    w.nslot = nslot;
+    w.scratch_per = scratch_per;
+    w.cap_B = capB;
+    w.last = st;
+    return MRA_OK;
+}
+
 extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double* theta, int64_t B,
                           double* loglik, void* stream) {
     if (!t || !theta || !loglik || B < 1) return fail(MRA_EINVAL, "NULL argument or B < 1");
@@ -382,52 +479,29 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const bool dev = is_device_ptr(theta);
     if (dev != is_device_ptr(loglik)) return fail(MRA_EINVAL, "theta and loglik must be in the same memory space");
-    std::vector<double> th(3 * B);
-    if (dev) {
-        if (hipMemcpy(th.data(), theta, 3 * B * 8, hipMemcpyDeviceToHost) != hipSuccess)
-            return fail(MRA_EDEVICE, "theta copy failed");
-    } else {
-        std::memcpy(th.data(), theta, 3 * B * 8);
+    if (!dev) {
+        for (int64_t b = 0; b < B; ++b) {
+            const double* q = theta + 3 * b;
+            if (!(q[0] > 0.0) || !(q[1] > 0.0) || !(q[2] > 0.0) || !std::isfinite(q[0]) || !std::isfinite(q[1]) ||
+                !std::isfinite(q[2]))
+                return fail(MRA_EINVAL, "theta " + std::to_string(b) + ": alpha, beta, tau must be finite and > 0");
+        }
     }
-    for (int64_t b = 0; b < B; ++b)
-        if (!(th[3 * b] > 0.0) || !(th[3 * b + 1] > 0.0) || !(th[3 * b + 2] > 0.0) || !std::isfinite(th[3 * b]) ||
-            !std::isfinite(th[3 * b + 1]) || !std::isfinite(th[3 * b + 2]))
-            return fail(MRA_EINVAL, "theta " + std::to_string(b) + ": alpha, beta, tau must be finite and > 0");
-
     const int M = h.M, P = h.P;
-    // per-theta device footprint (doubles)
     const int64_t F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
-    const int64_t per_theta = t->vst_size + F_stride + t->gram_size + h.nreg;
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(MRA_EDEVICE, "hipMemGetInfo failed");
-    const double budget = 0.55 * double(free_b) / 8.0;  // doubles
-    const int64_t scratch_per = std::max<int64_t>({t->scratch_leaf, t->scratch_fold, 1});
-    int64_t nslot = std::min<int64_t>(2048, std::max<int64_t>(1, int64_t(0.25 * budget / double(scratch_per))));
-    const double left = budget - double(nslot) * double(scratch_per);
-    int64_t Bc = std::min<int64_t>(B, int64_t(left / double(per_theta)));
-    if (Bc < 1) return fail(MRA_ENOMEM, "not enough device memory for one theta");
 
-    double *d_th = nullptr, *d_out = nullptr, *vst = nullptr, *F = nullptr, *gram = nullptr, *dval = nullptr,
-           *scratch = nullptr;
-    int* status = nullptr;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace& w = workspace_of(t);
+    rc = ensure_workspace(t, w, B, st);
+    if (rc) return rc;
+    if (w.used && w.last != st) (void)hipStreamWaitEvent(st, w.done, 0);
+    const int64_t Bc = w.Bc, nslot = w.nslot;
+    double* d_th = dev ? const_cast<double*>(theta) : w.th;
+    double* d_out = dev ? loglik : w.out;
+    int* status = w.status;
     std::vector<int> hstatus;
     KArgs a{};
-    const int64_t nprev_theta = 0;
-    (void)nprev_theta;
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&vst), Bc * t->vst_size * 8, st));
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&F), Bc * F_stride * 8, st));
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&gram), Bc * t->gram_size * 8, st));
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&dval), Bc * h.nreg * 8, st));
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&scratch), nslot * scratch_per * 8, st));
-    HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&status), B * sizeof(int), st));
-    if (!dev) {
-        HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&d_th), 3 * B * 8, st));
-        HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&d_out), B * 8, st));
-        HIPCHK(hipMemcpyAsync(d_th, theta, 3 * B * 8, hipMemcpyHostToDevice, st));
-    } else {
-        d_th = const_cast<double*>(theta);
-        d_out = loglik;
-    }
+    if (!dev) HIPCHK(hipMemcpyAsync(d_th, theta, 3 * B * 8, hipMemcpyHostToDevice, st));
     HIPCHK(launch_fill_int(status, B, 0, st));
 
     a.x = t->d_x; a.y = t->d_y; a.z = t->d_z; a.box = t->d_box;
@@ -436,11 +510,11 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
     for (int m = 0; m <= M && m <= MAXL; ++m) a.lvl[m] = h.lvl_start[m];
     a.J = h.J; a.M = M; a.nx = h.nx; a.ny = h.ny; a.rhat = h.rhat; a.P = P; a.WF = t->WF; a.WFs = t->WFs;
     a.offset = h.offset; a.smooth = smooth;
-    a.vst = vst; a.vst_stride = t->vst_size;
-    a.F = F; a.F_stride = F_stride;
-    a.gram = gram; a.gram_stride = t->gram_size;
-    a.dval = dval; a.d_stride = h.nreg;
-    a.scratch = scratch; a.scratch_stride = scratch_per;
+    a.vst = w.vst; a.vst_stride = t->vst_size;
+    a.F = w.F; a.F_stride = F_stride;
+    a.gram = w.gram; a.gram_stride = t->gram_size;
+    a.dval = w.dval; a.d_stride = h.nreg;
+    a.scratch = w.scratch; a.scratch_stride = w.scratch_per;
     a.n_used = double(h.n_used);
 
     for (int64_t b0 = 0; b0 < B; b0 += Bc) {
@@ -449,33 +523,48 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
         a.ntheta = nb;
         a.status = status + b0;
         a.out = d_out + b0;
-        HIPCHK(launch_fill(dval, int64_t(nb) * h.nreg, 0.0, st));
+        HIPCHK(launch_fill(w.dval, int64_t(nb) * h.nreg, 0.0, st));
         for (int m = 1; m < M; ++m) {
             a.level = m;
             a.tasks = t->d_prior[m];
             a.ntasks = int64_t(t->prior_tasks[m].size());
             if (a.ntasks == 0) continue;
-            const int64_t tot = a.ntasks * nb;
-            HIPCHK(timed(0, m, t->fl_prior[m] * nb, st, [&] { return launch_prior(a, int(std::min<int64_t>(tot, 1 << 16)), st); }));
+            const int grid = int(std::min<int64_t>(a.ntasks * nb, 1 << 16));
+            if (m > 1) HIPCHK(timed(0, m, t->fl_chain[m] * nb, st, [&] { return launch_chain(a, 0, grid, st); }));
+            HIPCHK(timed(1, m, t->fl_pfin[m] * nb, st, [&] { return launch_prior_finish(a, grid, st); }));
+        }
+        if (M > 1 && !t->prior_tasks[M - 1].empty()) {
+            a.level = M - 1;
+            a.tasks = t->d_prior[M - 1];
+            a.ntasks = int64_t(t->prior_tasks[M - 1].size());
+            const int grid = int(std::min<int64_t>(a.ntasks * nb, 1 << 16));
+            HIPCHK(timed(0, M, t->fl_chain[M] * nb, st, [&] { return launch_chain(a, 1, grid, st); }));
         }
         a.level = M;
+        a.tasks = t->d_small;
+        a.ntasks = int64_t(t->small_tasks.size());
+        if (a.ntasks > 0)
+            HIPCHK(timed(6, M, t->fl_small * nb, st, [&] { return launch_leaf_small(a, int(std::min<int64_t>(a.ntasks * nb, 1 << 18)), st); }));
         a.tasks = t->d_leaf;
         a.ntasks = int64_t(t->leaf_tasks.size());
         if (a.ntasks > 0)
-            HIPCHK(timed(1, M, t->fl_leaf * nb, st, [&] { return launch_leaf(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st); }));
+            HIPCHK(timed(2, M, t->fl_leaf * nb, st, [&] { return launch_leaf(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st); }));
         for (int m = M - 1; m >= 1; --m) {
             a.level = m;
             a.tasks = t->d_factor[m];
             a.ntasks = int64_t(t->factor_tasks[m].size());
             if (a.ntasks > 0)
-                HIPCHK(timed(2, m, t->fl_factor[m] * nb, st, [&] { return launch_fold_factor(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st); }));
+                HIPCHK(timed(3, m, t->fl_factor[m] * nb, st, [&] { return launch_fold_factor(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st); }));
             a.tasks = t->d_gramt[m];
             a.ntasks = int64_t(t->gram_tasks[m].size());
             if (a.ntasks > 0)
-                HIPCHK(timed(3, m, t->fl_gram[m] * nb, st, [&] { return launch_fold_gram(a, int(std::min<int64_t>(a.ntasks * nb, 1 << 16)), st); }));
+                HIPCHK(timed(4, m, t->fl_gram[m] * nb, st, [&] { return launch_fold_gram(a, int(std::min<int64_t>(a.ntasks * nb, 1 << 16)), st); }));
         }
-        HIPCHK(timed(4, 0, 0.0, st, [&] { return launch_final(a, h.nreg, t->root_gram, st); }));
+        HIPCHK(timed(5, 0, 0.0, st, [&] { return launch_final(a, h.nreg, t->root_gram, st); }));
     }
+    (void)hipEventRecord(w.done, st);
+    w.last = st;
+    w.used = true;
     if (!dev) {
         HIPCHK(hipMemcpyAsync(loglik, d_out, B * 8, hipMemcpyDeviceToHost, st));
         hstatus.resize(B);
@@ -491,15 +580,22 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
             }
     }
 done:
-    for (void* p : {static_cast<void*>(vst), static_cast<void*>(F), static_cast<void*>(gram),
-                    static_cast<void*>(dval), static_cast<void*>(scratch), static_cast<void*>(status)})
-        if (p) (void)hipFreeAsync(p, st);
-    if (!dev) {
-        if (d_th) (void)hipFreeAsync(d_th, st);
-        if (d_out) (void)hipFreeAsync(d_out, st);
-        (void)hipStreamSynchronize(st);
-    }
     return rc;
+}
+
+static Workspace& workspace_of(const mra_tree* t) {
+    auto* mt = const_cast<mra_tree*>(t);
+    if (!mt->ws) mt->ws = new Workspace();
+    return *static_cast<Workspace*>(mt->ws);
+}
+
+mra_tree::~mra_tree() {
+    if (ws) {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        static_cast<Workspace*>(ws)->release();
+        delete static_cast<Workspace*>(ws);
+    }
+    free_device();
 }
 
 extern "C" int mra_predict(const mra_tree* t, int family, double nu, const double* theta, const double* px,

@@ -2,15 +2,23 @@
 //
 // Per chunk of covariance-parameter vectors theta, the host launches, in
 // order (all regions of a level and all theta of the chunk in one launch):
-//   k_prior   levels 1 .. M-1 : whitened prior factors of every region's knots
-//   k_leaf    level M         : finest-level factors F = L_S^{-1} [V | z]
-//   k_fold_*  levels M-1 .. 1 : fold of the children's statistics, either in
-//                               observation space (factor form) or in knot
-//                               space (Gram form)
-//   k_final                   : log-likelihood per theta
+//   level m = 1 .. M-1:
+//     k_chain (knots)  : whitened prior rows of every level-m region's knots
+//     k_prior_finish   : C_m(Q_R, Q_R), its Cholesky factor and that factor's
+//                        inverse (the only thing descendants need of R)
+//   k_chain (obs)      : whitened prior rows of every observation, one task
+//                        per level-(M-1) region (its leaves share the path)
+//   k_leaf_finish      : finest-level factors F = L_S^{-1} [V | z], d = log det S
+//   level m = M-1 .. 1 : k_fold_factor / k_fold_gram (observation-space or
+//                        knot-space fold of the children's statistics)
+//   k_final            : log-likelihood per theta
 // The recursion is the remainder-covariance recursion of Sec. 1.1 written in
 // whitened form; its posterior statistics are the conditional (co)variances
 // the paper keeps per region (ATilde, Sec. 4.2 / Appendix B).
+//
+// Dense contractions run on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16]
+// and holds D[l/16 + 4i][l%16], i = 0..3, of the 16x16 result).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -20,6 +28,12 @@
 #include "mra_kernels.h"
 
 namespace mra {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // ------------------------------------------------------------------ helpers
 
@@ -41,18 +55,19 @@ __device__ __forceinline__ double grid_bar(double lo, double hi, int nb, double 
     return (lo + f * L) + ((double(p) * L) * (1.0 - 2.0 * f)) / double(nb - 1);
 }
 
-// Knots of region g into LDS arrays kx, ky (P entries; padded ones unused).
-__device__ void region_knots(const KArgs& a, int64_t g, double* kx, double* ky) {
+__device__ __forceinline__ void knot_xy(const KArgs& a, int64_t g, int i, double& kx, double& ky) {
     const double* b = a.box + 4 * g;
+    kx = grid_bar(b[0], b[1], a.nx, a.offset, i % a.nx);
+    ky = grid_bar(b[2], b[3], a.ny, a.offset, i / a.nx);
+}
+
+// Knots of region g into LDS arrays kx, ky (P entries; padded ones zero).
+__device__ __forceinline__ void region_knots(const KArgs& a, int64_t g, double* kx, double* ky) {
     for (int i = threadIdx.x; i < a.P; i += NT) {
-        if (i < a.rhat) {
-            const int p = i % a.nx, q = i / a.nx;
-            kx[i] = grid_bar(b[0], b[1], a.nx, a.offset, p);
-            ky[i] = grid_bar(b[2], b[3], a.ny, a.offset, q);
-        } else {
-            kx[i] = 0.0;
-            ky[i] = 0.0;
-        }
+        double x = 0.0, y = 0.0;
+        if (i < a.rhat) knot_xy(a, g, i, x, y);
+        kx[i] = x;
+        ky[i] = y;
     }
 }
 
@@ -67,130 +82,197 @@ __device__ __forceinline__ int64_t ancestor(const KArgs& a, int m, int64_t k, in
     return a.lvl[l - 1] + k / ipow_d(a.J, m - l);
 }
 
-__device__ void flag_fail(const KArgs& a, int th, int64_t g) {
+__device__ __forceinline__ void flag_fail(const KArgs& a, int th, int64_t g) {
     if (threadIdx.x == 0) atomicCAS(a.status + th, 0, int(g + 1));
 }
 
 // ---------------------------------------------------- workgroup primitives
 
-// C(r,c) +=/-= sum_k A(r,k) B(c,k) for r < R, c < N (c <= r when lower),
-// A(r,k) = A[r*sar + k*sak], B(c,k) = B[c*sbc + k*sbk], C row-major (ldc).
-// 64x64 output tiles, 4x4 per thread, K staged through LDS in chunks of 16.
-template <bool SUB>
-__device__ void wg_gemm(double* C, int64_t ldc, int R, int N, int K, const double* A, int64_t sar,
-                        int64_t sak, const double* B, int64_t sbc, int64_t sbk, bool lower,
-                        double* sm) {
+enum { MM_ADD = 0, MM_SUB = 1, MM_SET = 2 };
+constexpr int MK = 32;       // K chunk of the workgroup GEMM
+constexpr int MLD = TB + 1;  // LDS row pitch of the staged operands
+
+// Branch-free guarded load: reads p[off] when ok, else p[0], and returns 0 for
+// !ok.  Keeps masked loads unconditional so that batches of them are issued
+// back to back instead of one round trip at a time.  p itself must always be
+// a valid address (the start of the operand), never a per-lane pointer.
+__device__ __forceinline__ double ldg0(const double* p, int64_t off, bool ok) {
+    const double v = p[ok ? off : 0];
+    return ok ? v : 0.0;
+}
+
+// C(r,c) (+= | -= | =) sum_k A(r,k) B(c,k) over r < R, c < N (c <= r when
+// lower), A(r,k) = A[r*sar + k*sak], B(c,k) = B[c*sbc + k*sbk] (generic
+// pointers: global or LDS), C row-major (ldc).  64x64 output tiles: wave w
+// computes rows 16w..16w+15 with four 16x16 MFMA accumulators; K is staged
+// through LDS in chunks of 32, the next chunk's loads in flight (registers)
+// while the current one is multiplied.  With MM_SET an output tile may alias
+// the operand columns it is computed from (all reads precede its writes).
+template <int MODE>
+__device__ __forceinline__ void wg_mm(double* C, int64_t ldc, int R, int N, int K, const double* A, int64_t sar, int64_t sak,
+                      const double* B, int64_t sbc, int64_t sbk, bool lower, double* sm) {
+    constexpr int EPT = TB * MK / NT;  // staged elements per thread and operand
     double* As = sm;
-    double* Bs = sm + KC * TB;
-    const int tid = threadIdx.x, tr = tid / 16, tc = tid % 16;
+    double* Bs = sm + MK * MLD;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
+    const bool a_kfast = (sak == 1), b_kfast = (sbk == 1);
     for (int r0 = 0; r0 < R; r0 += TB)
         for (int c0 = 0; c0 < N; c0 += TB) {
             if (lower && c0 > r0 + TB - 1) continue;
-            double acc[4][4];
+            v4d acc[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int ct = 0; ct < 4; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+            // Thread tid stages elements e = tid + j*NT, j < EPT.  With k fastest
+            // (stride 1) they are (row tid/MK + j*NT/MK, k tid%MK), else
+            // (row tid%TB, k tid/TB + j*NT/TB): an arithmetic progression.
+            const int ar = a_kfast ? tid / MK : tid % TB, ak = a_kfast ? tid % MK : tid / TB;
+            const int br = b_kfast ? tid / MK : tid % TB, bk = b_kfast ? tid % MK : tid / TB;
+            const int adr = a_kfast ? NT / MK : 0, adk = a_kfast ? 0 : NT / TB;
+            const int bdr = b_kfast ? NT / MK : 0, bdk = b_kfast ? 0 : NT / TB;
+            double ra[EPT], rb[EPT];
+            auto fetch = [&](int k0) {
+                const double* pa = A + int64_t(r0 + ar) * sar + int64_t(k0 + ak) * sak;
+                const double* pb = B + int64_t(c0 + br) * sbc + int64_t(k0 + bk) * sbk;
+                const int64_t sa = int64_t(adr) * sar + int64_t(adk) * sak;
+                const int64_t sb = int64_t(bdr) * sbc + int64_t(bdk) * sbk;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-            for (int k0 = 0; k0 < K; k0 += KC) {
-                for (int e = tid; e < TB * KC; e += NT) {
-                    int r, k;
-                    if (sak == 1) { r = e / KC; k = e % KC; } else { k = e / TB; r = e % TB; }
-                    double v = 0.0;
-                    if (r0 + r < R && k0 + k < K) v = A[int64_t(r0 + r) * sar + int64_t(k0 + k) * sak];
-                    As[k * TB + r] = v;
-                    int c, kb;
-                    if (sbk == 1) { c = e / KC; kb = e % KC; } else { kb = e / TB; c = e % TB; }
-                    double w = 0.0;
-                    if (c0 + c < N && k0 + kb < K) w = B[int64_t(c0 + c) * sbc + int64_t(k0 + kb) * sbk];
-                    Bs[kb * TB + c] = w;
+                for (int j = 0; j < EPT; ++j) {
+                    const bool oka = (r0 + ar + j * adr < R) && (k0 + ak + j * adk < K);
+                    const bool okb = (c0 + br + j * bdr < N) && (k0 + bk + j * bdk < K);
+                    const double va = *(oka ? pa + j * sa : A);
+                    const double vb = *(okb ? pb + j * sb : B);
+                    ra[j] = oka ? va : 0.0;
+                    rb[j] = okb ? vb : 0.0;
                 }
+            };
+            fetch(0);
+            for (int k0 = 0; k0 < K; k0 += MK) {
                 __syncthreads();
 #pragma unroll
-                for (int k = 0; k < KC; ++k) {
-                    double av[4], bv[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) { av[i] = As[k * TB + tr * 4 + i]; bv[i] = Bs[k * TB + tc * 4 + i]; }
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+                for (int j = 0; j < EPT; ++j) {
+                    As[(ak + j * adk) * MLD + ar + j * adr] = ra[j];
+                    Bs[(bk + j * bdk) * MLD + br + j * bdr] = rb[j];
                 }
                 __syncthreads();
+                if (k0 + MK < K) fetch(k0 + MK);
+#pragma unroll
+                for (int ks = 0; ks < MK / 4; ++ks) {
+                    const double av = As[(4 * ks + lg) * MLD + 16 * w + lr];
+#pragma unroll
+                    for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma(av, Bs[(4 * ks + lg) * MLD + 16 * ct + lr], acc[ct]);
+                }
+            }
+            // epilogue: batch the reads of C before any write
+            double cold[16];
+            if (MODE != MM_SET) {
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = r0 + 16 * w + lg + 4 * i, c = c0 + 16 * ct + lr;
+                        const bool ok = r < R && c < N && (!lower || c <= r);
+                        cold[4 * ct + i] = ldg0(C, int64_t(r) * ldc + c, ok);
+                    }
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int r = r0 + tr * 4 + i, c = c0 + tc * 4 + j;
+                for (int i = 0; i < 4; ++i) {
+                    const int r = r0 + 16 * w + lg + 4 * i, c = c0 + 16 * ct + lr;
                     if (r < R && c < N && (!lower || c <= r)) {
-                        double* p = C + int64_t(r) * ldc + c;
-                        *p = SUB ? (*p - acc[i][j]) : (*p + acc[i][j]);
+                        double v = acc[ct][i];
+                        if (MODE == MM_ADD) v = cold[4 * ct + i] + v;
+                        else if (MODE == MM_SUB) v = cold[4 * ct + i] - v;
+                        C[int64_t(r) * ldc + c] = v;
                     }
                 }
         }
     __syncthreads();
 }
 
-// In-place Cholesky of an n x n (n <= 64) lower triangle held in LDS (ld).
-// Returns true when a pivot is not positive (the factor is then garbage).
-__device__ bool wg_potrf_lds(double* T, int n, int ld, int* flag) {
-    const int tid = threadIdx.x;
-    if (tid == 0) *flag = 0;
-    __syncthreads();
+// ------------------------------------------------- wave-level primitives
+// A wavefront executes in lockstep and its LDS accesses complete in order;
+// wsync() only keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Cholesky of an n x n (n <= 64) lower triangle in LDS by one wave (lane r
+// owns row r).  Returns true on a non-positive pivot.
+__device__ __forceinline__ bool wave_potrf(double* T, int ld, int n) {
+    const int lane = threadIdx.x & 63;
+    bool bad = false;
     for (int j = 0; j < n; ++j) {
-        if (tid == 0) {
-            double d = T[j * ld + j];
-            if (!(d > 0.0)) { *flag = 1; d = 1.0; }
-            T[j * ld + j] = sqrt(d);
+        wsync();
+        double d = T[j * ld + j];
+        if (!(d > 0.0)) { bad = true; d = 1.0; }
+        d = sqrt(d);
+        wsync();
+        if (lane == j) T[j * ld + j] = d;
+        double lij = 0.0;
+        if (lane > j && lane < n) {
+            lij = T[lane * ld + j] / d;
+            T[lane * ld + j] = lij;
         }
-        __syncthreads();
-        const double djj = T[j * ld + j];
-        for (int i = j + 1 + tid; i < n; i += NT) T[i * ld + j] /= djj;
-        __syncthreads();
-        const int m = n - j - 1;
-        for (int e = tid; e < m * m; e += NT) {
-            const int i = j + 1 + e / m, k = j + 1 + e % m;
-            if (k <= i) T[i * ld + k] -= T[i * ld + j] * T[k * ld + j];
-        }
-        __syncthreads();
+        wsync();
+        if (lane > j && lane < n)
+            for (int k = j + 1; k <= lane; ++k) T[lane * ld + k] = fma(-lij, T[k * ld + j], T[lane * ld + k]);
     }
+    wsync();
+    return bad;
+}
+
+// Li <- L^{-1} (n x n, n <= 64, lower) by one wave (lane j owns column j).
+__device__ __forceinline__ void wave_trinv(const double* L, int ld, double* Li, int64_t ld2, int n) {
+    const int j = threadIdx.x & 63;
+    for (int r = 0; r < n; ++r) {
+        if (j <= r) {
+            double s = (r == j) ? 1.0 : 0.0;
+            for (int k = j; k < r; ++k) s = fma(-L[r * ld + k], Li[k * ld2 + j], s);
+            Li[r * ld2 + j] = s / L[r * ld + r];
+        } else if (j < n) {
+            Li[r * ld2 + j] = 0.0;
+        }
+        wsync();
+    }
+}
+
+// In-place Cholesky of an n x n (n <= 64) lower triangle held in LDS (ld),
+// done by wave 0 while the others wait.  Returns true (in every thread) when
+// a pivot is not positive (the factor is then garbage).
+__device__ __forceinline__ bool wg_potrf_lds(double* T, int n, int ld, int* flag) {
+    if ((threadIdx.x >> 6) == 0) {
+        const bool bad = wave_potrf(T, ld, n);
+        if (threadIdx.x == 0) *flag = bad ? 1 : 0;
+    }
+    __syncthreads();
     const bool bad = *flag != 0;
     __syncthreads();
     return bad;
 }
 
-// Forward substitution L v = w for one vector of length n <= 64 whose entries
-// sit at v[i*stride]; L in LDS (lower, ld).  Registers hold the vector.
-__device__ __forceinline__ void tri_solve_vec(const double* L, int ld, int n, double* v, int64_t stride) {
-    double x[64];
-#pragma unroll
-    for (int r = 0; r < 64; ++r) {
-        if (r < n) {
-            double s = v[int64_t(r) * stride];
-#pragma unroll
-            for (int k = 0; k < r; ++k) s = fma(-L[r * ld + k], x[k], s);
-            x[r] = s / L[r * ld + r];
-            v[int64_t(r) * stride] = x[r];
-        }
-    }
-}
-
-// X (R x n, row-major ldx) <- X L^{-T}, L (n x n, n <= 64) in LDS.
-__device__ void wg_trsm_rlt(double* X, int64_t ldx, int R, const double* L, int ld, int n) {
-    for (int a = threadIdx.x; a < R; a += NT) tri_solve_vec(L, ld, n, X + int64_t(a) * ldx, 1);
+// Li <- L^{-1} for an n x n (n <= 64) lower-triangular L in LDS (the rest of
+// the 64 x 64 tile of Li is zero), by wave 0.
+__device__ __forceinline__ void wg_trinv_lds(const double* L, int ld, double* Li, int ld2, int n) {
+    for (int e = threadIdx.x; e < TB * TB; e += NT) Li[(e / TB) * ld2 + (e % TB)] = 0.0;
+    __syncthreads();
+    if ((threadIdx.x >> 6) == 0) wave_trinv(L, ld, Li, ld2, n);
     __syncthreads();
 }
 
-// Load an n x n lower triangle (global, ldg) into LDS (ld), zero above.
-__device__ void load_tile(double* T, int ld, const double* G, int64_t ldg, int n) {
-    for (int e = threadIdx.x; e < n * n; e += NT) {
-        const int i = e / n, j = e % n;
-        T[i * ld + j] = (j <= i) ? G[int64_t(i) * ldg + j] : 0.0;
+// Load an n x n lower triangle (global, ldg) into LDS (ld), zero elsewhere in
+// the 64 x 64 tile.
+__device__ __forceinline__ void load_tile(double* T, int ld, const double* G, int64_t ldg, int n) {
+    for (int e = threadIdx.x; e < TB * TB; e += NT) {
+        const int i = e / TB, j = e % TB;
+        T[i * ld + j] = (i < n && j <= i) ? G[int64_t(i) * ldg + j] : 0.0;
     }
     __syncthreads();
 }
 
-__device__ void store_tile(double* G, int64_t ldg, const double* T, int ld, int n) {
+__device__ __forceinline__ void store_tile(double* G, int64_t ldg, const double* T, int ld, int n) {
     for (int e = threadIdx.x; e < n * n; e += NT) {
         const int i = e / n, j = e % n;
         G[int64_t(i) * ldg + j] = (j <= i) ? T[i * ld + j] : 0.0;
@@ -198,173 +280,441 @@ __device__ void store_tile(double* G, int64_t ldg, const double* T, int ld, int 
     __syncthreads();
 }
 
-// Blocked right-looking Cholesky of an n x n lower triangle in global memory.
-// Accumulates sum(log diag) into *logdet (thread 0's copy).  Returns failure.
-__device__ bool wg_potrf_global(double* A, int64_t lda, int n, double* Ls, double* sm, int* flag,
-                                double* logdet) {
-    double ld_acc = 0.0;
+// Blocked right-looking Cholesky of an n x n lower triangle (generic pointer,
+// lda).  Diagonal blocks are factored and inverted in LDS; panels are solved
+// as products with the inverted block.  *logdet (all threads) = sum log diag.
+__device__ __forceinline__ bool wg_potrf(double* A, int64_t lda, int n, double* Ls, double* Li, double* sm, int* flag,
+                         double* red, double* logdet) {
+    double acc = 0.0;
     for (int j0 = 0; j0 < n; j0 += TB) {
         const int jb = min(TB, n - j0);
         double* Ajj = A + int64_t(j0) * lda + j0;
-        load_tile(Ls, TB + 1, Ajj, lda, jb);
-        if (wg_potrf_lds(Ls, jb, TB + 1, flag)) return true;
-        store_tile(Ajj, lda, Ls, TB + 1, jb);
-        if (threadIdx.x == 0)
-            for (int i = 0; i < jb; ++i) ld_acc += log(Ls[i * (TB + 1) + i]);
+        load_tile(Ls, MLD, Ajj, lda, jb);
+        if (wg_potrf_lds(Ls, jb, MLD, flag)) return true;
+        store_tile(Ajj, lda, Ls, MLD, jb);
+        for (int i = 0; i < jb; ++i) acc += log(Ls[i * MLD + i]);
         const int rest = n - j0 - jb;
         if (rest > 0) {
+            wg_trinv_lds(Ls, MLD, Li, MLD, jb);
             double* Aij = A + int64_t(j0 + jb) * lda + j0;
-            wg_trsm_rlt(Aij, lda, rest, Ls, TB + 1, jb);
-            wg_gemm<true>(A + int64_t(j0 + jb) * lda + j0 + jb, lda, rest, rest, jb, Aij, lda, 1, Aij,
-                          lda, 1, true, sm);
+            // panel: A_ij <- A_ij L_jj^{-T}
+            wg_mm<MM_SET>(Aij, lda, rest, jb, jb, Aij, lda, 1, Li, MLD, 1, false, sm);
+            // trailing update (lower)
+            wg_mm<MM_SUB>(A + int64_t(j0 + jb) * lda + j0 + jb, lda, rest, rest, jb, Aij, lda, 1, Aij, lda, 1,
+                          true, sm);
         }
     }
-    if (threadIdx.x == 0) *logdet = ld_acc;
+    (void)red;
+    *logdet = acc;
     return false;
 }
 
-// X (n x W, ldx) <- L^{-1} X with L (n x n lower, global, ldl).
-__device__ void wg_trsm_lln(const double* L, int64_t ldl, int n, double* X, int64_t ldx, int W,
-                            double* Ls, double* sm) {
+// X (n x W, ldx) <- L^{-1} X with L (n x n lower, generic pointer, ldl).
+// Diagonal blocks are inverted in LDS and applied as products.
+__device__ __forceinline__ void wg_trsm_lln(const double* L, int64_t ldl, int n, double* X, int64_t ldx, int W, double* Ls,
+                            double* Li, double* sm) {
     for (int i0 = 0; i0 < n; i0 += TB) {
         const int ib = min(TB, n - i0);
-        load_tile(Ls, TB + 1, L + int64_t(i0) * ldl + i0, ldl, ib);
-        for (int c = threadIdx.x; c < W; c += NT) tri_solve_vec(Ls, TB + 1, ib, X + int64_t(i0) * ldx + c, ldx);
-        __syncthreads();
+        load_tile(Ls, MLD, L + int64_t(i0) * ldl + i0, ldl, ib);
+        wg_trinv_lds(Ls, MLD, Li, MLD, ib);
+        double* Xi = X + int64_t(i0) * ldx;
+        // X_i <- Li X_i : C(r, c) = sum_k Li(r, k) X_i(k, c)
+        wg_mm<MM_SET>(Xi, ldx, ib, W, ib, Li, MLD, 1, Xi, 1, ldx, false, sm);
         const int rest = n - i0 - ib;
         if (rest > 0)
-            wg_gemm<true>(X + int64_t(i0 + ib) * ldx, ldx, rest, W, ib, L + int64_t(i0 + ib) * ldl + i0, ldl,
-                          1, X + int64_t(i0) * ldx, 1, ldx, false, sm);
-    }
-}
-
-// Whitened prior factors of R point rows (coordinates px/py; rows >= nreal
-// are padding) for ancestor levels 1..L (global indices anc[1..L], knots in
-// akx/aky, P per ancestor).  Block l of row a is written at
-//     dst0 + (l-1)*bstride + a*ldd  (P consecutive doubles).
-__device__ void chain(const KArgs& a, const double* th, int R, int nreal, const double* px,
-                      const double* py, int L, const int64_t* anc, const double* akx, const double* aky,
-                      const double* vst, double* dst0, int64_t bstride, int64_t ldd, double* Ls,
-                      double* sm) {
-    const int P = a.P;
-    const double alpha = th[0], inv_beta = 1.0 / th[1];
-    for (int l = 1; l <= L; ++l) {
-        double* dl = dst0 + int64_t(l - 1) * bstride;
-        const double* kx = akx + (l - 1) * P;
-        const double* ky = aky + (l - 1) * P;
-        for (int e = threadIdx.x; e < R * P; e += NT) {
-            const int r = e / P, b = e % P;
-            double v = 0.0;
-            if (r < nreal && b < a.rhat) v = cov_pts(px[r], py[r], kx[b], ky[b], alpha, inv_beta, a.smooth);
-            dl[int64_t(r) * ldd + b] = v;
-        }
-        __syncthreads();
-        const double* Vanc = vst + a.vst_off[anc[l]];
-        for (int i = 1; i < l; ++i)
-            wg_gemm<true>(dl, ldd, R, P, P, dst0 + int64_t(i - 1) * bstride, ldd, 1,
-                          Vanc + int64_t(i - 1) * P * P, P, 1, false, sm);
-        load_tile(Ls, TB + 1, Vanc + int64_t(l - 1) * P * P, P, P);
-        wg_trsm_rlt(dl, ldd, R, Ls, TB + 1, P);
+            wg_mm<MM_SUB>(X + int64_t(i0 + ib) * ldx, ldx, rest, W, ib, L + int64_t(i0 + ib) * ldl + i0, ldl, 1,
+                          Xi, 1, ldx, false, sm);
     }
 }
 
 // ------------------------------------------------------------------ kernels
 
 struct Smem {
-    double gemm[2 * KC * TB];
-    double L[TB * (TB + 1)];
-    double akx[MAXL * TB], aky[MAXL * TB];
+    double mm[2 * MK * MLD];
+    double L[TB * MLD];
+    double Li[TB * MLD];
     double kx[TB], ky[TB];
-    double red[NT];
     int flag;
 };
 
-// Prior of every region at `level` (< M) for every theta of the chunk.
-__global__ void __launch_bounds__(NT) k_prior(KArgs a) {
-    __shared__ Smem s;
-    const int64_t total = a.ntasks * a.ntheta;
-    const int m = a.level, P = a.P;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const int th = int(t / a.ntasks);
-        const int64_t g = a.tasks[t % a.ntasks];
-        const int64_t k = g - a.lvl[m - 1];  // index within level
-        const double* thp = a.theta + 3 * th;
-        const double* vst = a.vst + th * a.vst_stride;
-        int64_t anc[MAXL + 1];
-        for (int l = 1; l <= m; ++l) anc[l] = ancestor(a, m, k, l);
-        for (int l = 1; l < m; ++l) region_knots(a, anc[l], s.akx + (l - 1) * P, s.aky + (l - 1) * P);
-        region_knots(a, g, s.kx, s.ky);
-        __syncthreads();
-        double* mine = a.vst + th * a.vst_stride + a.vst_off[g];
-        chain(a, thp, P, a.rhat, s.kx, s.ky, m - 1, anc, s.akx, s.aky, vst, mine, int64_t(P) * P, P, s.L, s.gemm);
-        // C_m(Q_R, Q_R) = C(Q_R, Q_R) - sum_{i<m} V^i V^i^T, padded with an identity block
-        double* W = mine + int64_t(m - 1) * P * P;
-        const double alpha = thp[0], inv_beta = 1.0 / thp[1];
-        for (int e = threadIdx.x; e < P * P; e += NT) {
-            const int i = e / P, j = e % P;
-            double v;
-            if (i < a.rhat && j < a.rhat) v = cov_pts(s.kx[i], s.ky[i], s.kx[j], s.ky[j], alpha, inv_beta, a.smooth);
-            else v = (i == j) ? 1.0 : 0.0;
-            W[e] = v;
+// Whitened prior rows.  mode 0: the r_hat knots of every level-m region
+// (a.level = m) for ancestors 1..m-1, written into the region's V store
+// (row-major P x mP, block i-1 = V^i).  mode 1: every observation under a
+// level-(M-1) region for ancestors 1..M-1, written into the F buffer (block of
+// level l at columns (M-1-l)P).  For ancestor level l, with C the covariance:
+//     V^l = ( C(rows, Q_{A_l}) - sum_{i<l} V^i V^i(Q_{A_l})^T ) L_{A_l}^{-T}.
+// Each wave owns 16 rows.  Ancestor levels are taken in groups of GS = 256/P:
+// one pending accumulator per level of the group (MFMA destinations, knots x
+// rows) receives the covariance, the contributions of all earlier groups (their
+// V rows read back from memory) and, right-looking, those of the group's own
+// earlier levels.  A V^i in accumulator layout serves directly as the B
+// operand: the summation index is permuted consistently on the A operand,
+// which is staged in LDS one P x P block at a time.
+// Stage a P x P block (row-major, ld; rows 16-byte aligned) into LDS
+// transposed with an odd pitch: blk[c * (P + 1) + r] = src[r][c], so that the
+// 16 lanes of a group, which read 16 consecutive rows r of one column c, hit
+// 16 different banks.  All loads of a thread are issued before any store.
+template <int P>
+__device__ __forceinline__ void stage_block(double* blk, const double* src, int64_t ld) {
+    constexpr int E2 = P * P / 2;                 // double2 elements
+    constexpr int PER = (E2 + NT - 1) / NT;
+    double2 tmp[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int e = threadIdx.x + j * NT;
+        const int r = (2 * e) / P, c = (2 * e) % P;
+        const bool ok = e < E2;
+        tmp[j] = *reinterpret_cast<const double2*>(src + (ok ? int64_t(r) * ld + c : 0));
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int e = threadIdx.x + j * NT;
+        if (e < E2) {
+            const int r = (2 * e) / P, c = (2 * e) % P;
+            blk[c * (P + 1) + r] = tmp[j].x;
+            blk[(c + 1) * (P + 1) + r] = tmp[j].y;
         }
-        __syncthreads();
-        for (int i = 1; i < m; ++i)
-            wg_gemm<true>(W, P, P, P, P, mine + int64_t(i - 1) * P * P, P, 1, mine + int64_t(i - 1) * P * P, P, 1,
-                          true, s.gemm);
-        load_tile(s.L, TB + 1, W, P, P);
-        if (wg_potrf_lds(s.L, P, TB + 1, &s.flag)) flag_fail(a, th, g);
-        store_tile(W, P, s.L, TB + 1, P);
     }
 }
 
-// Finest-level regions: factors F = L_S^{-1} [V^{M-1} .. V^1 | z] in place in
-// the F buffer rows of the leaf, and d = log det S.
-__global__ void __launch_bounds__(NT) k_leaf(KArgs a) {
-    __shared__ Smem s;
+template <int P>
+__global__ void __launch_bounds__(NT) k_chain(KArgs a, int mode) {
+    constexpr int NM = P / 16;
+    constexpr int GS = 256 / P;
+    __shared__ double blk[P * (P + 1)];
+    __shared__ double akx[MAXL * P], aky[MAXL * P];
+    __shared__ int64_t voff[MAXL];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
     const int64_t total = a.ntasks * a.ntheta;
-    const int M = a.M, P = a.P;
-    double* S = a.scratch + blockIdx.x * a.scratch_stride;
+    const int m = mode == 0 ? a.level : a.M - 1;  // level of the task region
+    const int L = mode == 0 ? m - 1 : a.M - 1;    // ancestor levels of the rows
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         const int th = int(t / a.ntasks);
         const int64_t g = a.tasks[t % a.ntasks];
-        const int64_t k = g - a.lvl[M - 1];
-        const int64_t lo = a.obs_lo[g];
-        const int n = int(a.obs_hi[g] - lo);
+        const int64_t k = g - a.lvl[m - 1];
         const double* thp = a.theta + 3 * th;
+        const double alpha = thp[0], inv_beta = 1.0 / thp[1];
         const double* vst = a.vst + th * a.vst_stride;
-        double* Frows = a.F + th * a.F_stride + lo * a.WFs;
-        int64_t anc[MAXL + 1];
-        for (int l = 1; l < M; ++l) anc[l] = ancestor(a, M, k, l);
-        for (int l = 1; l < M; ++l) region_knots(a, anc[l], s.akx + (l - 1) * P, s.aky + (l - 1) * P);
-        for (int r = threadIdx.x; r < n; r += NT) Frows[int64_t(r) * a.WFs + (a.WF - 1)] = a.z[lo + r];
+        if (tid < L) voff[tid] = a.vst_off[ancestor(a, m, k, tid + 1)];
+        for (int l = 0; l < L; ++l) region_knots(a, ancestor(a, m, k, l + 1), akx + l * P, aky + l * P);
         __syncthreads();
-        if (M > 1)
-            chain(a, thp, n, n, a.x + lo, a.y + lo, M - 1, anc, s.akx, s.aky, vst, Frows + int64_t(M - 2) * P,
-                  -int64_t(P), a.WFs, s.L, s.gemm);
-        // S = C(S,S) - sum_l V^l V^l^T + tau I  (lower)
-        const double alpha = thp[0], inv_beta = 1.0 / thp[1], tau = thp[2];
-        const double* px = a.x + lo;
-        const double* py = a.y + lo;
-        for (int64_t e = threadIdx.x; e < int64_t(n) * n; e += NT) {
-            const int i = int(e / n), j = int(e % n);
-            if (j <= i) {
-                double v = cov_pts(px[i], py[i], px[j], py[j], alpha, inv_beta, a.smooth);
-                if (i == j) v += tau;
-                S[e] = v;
+        int nrows;
+        int64_t lo = 0, ldd;
+        double* dst;
+        if (mode == 0) {
+            nrows = P;
+            ldd = int64_t(m) * P;
+            dst = a.vst + th * a.vst_stride + a.vst_off[g];
+        } else {
+            lo = a.obs_lo[g];
+            nrows = int(a.obs_hi[g] - lo);
+            ldd = a.WFs;
+            dst = a.F + th * a.F_stride + lo * a.WFs;
+        }
+        for (int r0 = 0; r0 < nrows; r0 += 64) {
+            const int rr = r0 + 16 * w + lr;
+            const bool valid = rr < nrows && (mode == 1 || rr < a.rhat);
+            const bool store = mode == 0 ? (rr < P) : (rr < nrows);
+            double px = 0.0, py = 0.0;
+            if (valid) {
+                if (mode == 1) { px = a.x[lo + rr]; py = a.y[lo + rr]; }
+                else knot_xy(a, g, rr, px, py);
+            }
+            double* drow = dst + int64_t(rr) * ldd;
+            auto colof = [&](int i) -> int64_t { return mode == 0 ? int64_t(i) * P : int64_t(a.M - 2 - i) * P; };
+            for (int g0 = 0; g0 < L; g0 += GS) {
+                v4d acc[GS][NM];
+#pragma unroll
+                for (int l = 0; l < GS; ++l)
+#pragma unroll
+                    for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int q = 16 * mt + lg + 4 * i;
+                            const int la = g0 + l;
+                            acc[l][mt][i] = (la < L && valid && q < a.rhat)
+                                                ? cov_pts(akx[la * P + q], aky[la * P + q], px, py, alpha, inv_beta, a.smooth)
+                                                : 0.0;
+                        }
+                // earlier groups: acc_l -= V^{i+1}(Q_{A_l}) V^{i+1}
+                for (int i = 0; i < g0; ++i) {
+                    v4d vi[NM];
+                    // base: the task's first row (always inside the buffer); masked
+                    // lanes read that row's first element instead of their own
+                    const int64_t roff = int64_t(rr) * ldd + colof(i);
+#pragma unroll
+                    for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) vi[mt][q] = ldg0(dst, roff + 16 * mt + lg + 4 * q, valid);
+#pragma unroll
+                    for (int l = 0; l < GS; ++l) {
+                        if (g0 + l < L) {
+                            __syncthreads();
+                            stage_block<P>(blk, vst + voff[g0 + l] + int64_t(i) * P, int64_t(g0 + l + 1) * P);
+                            __syncthreads();
+#pragma unroll
+                            for (int mt2 = 0; mt2 < NM; ++mt2)
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) {
+                                    const double bv = vi[mt2][q];
+#pragma unroll
+                                    for (int mt = 0; mt < NM; ++mt)
+                                        acc[l][mt] = mfma(-blk[(16 * mt2 + lg + 4 * q) * (P + 1) + 16 * mt + lr], bv, acc[l][mt]);
+                                }
+                        }
+                    }
+                }
+                // this group, right-looking
+#pragma unroll
+                for (int i = 0; i < GS; ++i) {
+                    if (g0 + i < L) {
+                        const int li = g0 + i;
+                        __syncthreads();
+                        stage_block<P>(blk, vst + voff[li] + int64_t(li) * P, int64_t(li + 1) * P);
+                        __syncthreads();
+                        v4d vi[NM];
+#pragma unroll
+                        for (int mt = 0; mt < NM; ++mt) {
+                            v4d vn = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                            for (int mt2 = 0; mt2 <= mt; ++mt2)
+#pragma unroll
+                                for (int q = 0; q < 4; ++q)
+                                    vn = mfma(blk[(16 * mt2 + lg + 4 * q) * (P + 1) + 16 * mt + lr], acc[i][mt2][q], vn);
+                            vi[mt] = vn;
+                        }
+                        if (store) {
+                            double* d = drow + colof(li);
+#pragma unroll
+                            for (int mt = 0; mt < NM; ++mt)
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) d[16 * mt + lg + 4 * q] = vi[mt][q];
+                        }
+#pragma unroll
+                        for (int l = i + 1; l < GS; ++l) {
+                            if (g0 + l < L) {
+                                __syncthreads();
+                                stage_block<P>(blk, vst + voff[g0 + l] + int64_t(li) * P, int64_t(g0 + l + 1) * P);
+                                __syncthreads();
+#pragma unroll
+                                for (int mt2 = 0; mt2 < NM; ++mt2)
+#pragma unroll
+                                    for (int q = 0; q < 4; ++q) {
+                                        const double bv = vi[mt2][q];
+#pragma unroll
+                                        for (int mt = 0; mt < NM; ++mt)
+                                            acc[l][mt] = mfma(-blk[(16 * mt2 + lg + 4 * q) * (P + 1) + 16 * mt + lr], bv, acc[l][mt]);
+                                    }
+                            }
+                        }
+                    }
+                }
             }
         }
         __syncthreads();
-        for (int l = 1; l < M; ++l) {
-            const double* Vl = Frows + int64_t(M - 1 - l) * P;
-            wg_gemm<true>(S, n, n, n, P, Vl, a.WFs, 1, Vl, a.WFs, 1, true, s.gemm);
+    }
+}
+
+// Level-m regions, one wave per region: W = C(Q_R, Q_R) - sum_{i<m} V^i V^i^T
+// (lower 16x16 tiles on the matrix cores, padded with an identity block), its
+// Cholesky factor and inverse; the inverse is stored as the last block of the
+// region's V store.
+template <int P>
+__global__ void __launch_bounds__(NT) k_prior_finish_w(KArgs a) {
+    constexpr int NM = P / 16, NT2 = NM * (NM + 1) / 2;
+    constexpr int LDT = P + 1;
+    __shared__ double T[4][P * LDT];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const int64_t total = a.ntasks * a.ntheta;
+    const int m = a.level;
+    double* Tw = T[w];
+    for (int64_t t = int64_t(blockIdx.x) * 4 + w; t < total; t += int64_t(gridDim.x) * 4) {
+        const int th = int(t / a.ntasks);
+        const int64_t g = a.tasks[t % a.ntasks];
+        const double* thp = a.theta + 3 * th;
+        const double alpha = thp[0], inv_beta = 1.0 / thp[1];
+        double* V = a.vst + th * a.vst_stride + a.vst_off[g];
+        const int64_t ld = int64_t(m) * P;
+        v4d acc[NT2];
+#pragma unroll
+        for (int e = 0; e < NT2; ++e) acc[e] = v4d{0.0, 0.0, 0.0, 0.0};
+        const int K = (m - 1) * P;
+        for (int kb = 0; kb < K; kb += 16) {
+            v4d fr[NM];
+#pragma unroll
+            for (int rt = 0; rt < NM; ++rt)
+                fr[rt] = *reinterpret_cast<const v4d*>(V + int64_t(16 * rt + lr) * ld + kb + 4 * lg);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int e = 0;
+#pragma unroll
+                for (int rt = 0; rt < NM; ++rt)
+#pragma unroll
+                    for (int ct = 0; ct <= rt; ++ct) acc[e] = mfma(fr[rt][j], fr[ct][j], acc[e]), ++e;
+            }
         }
+        // W = C - acc into LDS (lower), identity in the padding
+        double kx_r[4], ky_r[4];
+        {
+            int e = 0;
+#pragma unroll
+            for (int rt = 0; rt < NM; ++rt)
+#pragma unroll
+                for (int ct = 0; ct <= rt; ++ct) {
+                    const int c = 16 * ct + lr;
+                    double cx = 0.0, cy = 0.0;
+                    if (c < a.rhat) knot_xy(a, g, c, cx, cy);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = 16 * rt + lg + 4 * i;
+                        double v;
+                        if (r < a.rhat && c < a.rhat) {
+                            knot_xy(a, g, r, kx_r[i], ky_r[i]);
+                            v = cov_pts(kx_r[i], ky_r[i], cx, cy, alpha, inv_beta, a.smooth) - acc[e][i];
+                        } else {
+                            v = (r == c) ? 1.0 : 0.0;
+                        }
+                        if (c <= r) Tw[r * LDT + c] = v;
+                    }
+                    ++e;
+                }
+        }
+        wsync();
+        if (wave_potrf(Tw, LDT, P) && lane == 0) atomicCAS(a.status + th, 0, int(g + 1));
+        // the inverse goes straight to its place (lane j writes and rereads column j)
+        wave_trinv(Tw, LDT, V + (m - 1) * P, ld, P);
+        wsync();
+    }
+}
+
+// Finest-level regions with at most 16 observations, one wave per region:
+// S = C(S,S) - sum_l V^l V^l^T + tau I on the matrix cores (one 16x16 tile),
+// in-wave Cholesky, d = log det S, L^{-1}, and F <- L^{-1} [V | z] in
+// 16-column tiles.
+__global__ void __launch_bounds__(NT) k_leaf_small(KArgs a) {
+    constexpr int LDT = 17;
+    __shared__ double T[4][16 * LDT];
+    __shared__ double Ti[4][16 * LDT];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const int64_t total = a.ntasks * a.ntheta;
+    const int M = a.M;
+    double* Tw = T[w];
+    double* Tiw = Ti[w];
+    for (int64_t t = int64_t(blockIdx.x) * 4 + w; t < total; t += int64_t(gridDim.x) * 4) {
+        const int th = int(t / a.ntasks);
+        const int64_t g = a.tasks[t % a.ntasks];
+        const int64_t lo = a.obs_lo[g];
+        const int n = int(a.obs_hi[g] - lo);
+        const double* thp = a.theta + 3 * th;
+        const double alpha = thp[0], inv_beta = 1.0 / thp[1], tau = thp[2];
+        double* Fr = a.F + th * a.F_stride + lo * a.WFs;
+        const int K = (M - 1) * a.P;
+        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int kb = 0; kb < K; kb += 16) {
+            v4d fr = v4d{0.0, 0.0, 0.0, 0.0};
+            if (lr < n) fr = *reinterpret_cast<const v4d*>(Fr + int64_t(lr) * a.WFs + kb + 4 * lg);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc = mfma(fr[j], fr[j], acc);
+        }
+        // S = C + tau I - acc (lower), identity beyond n
+        {
+            const int c = lr;
+            const double cx = c < n ? a.x[lo + c] : 0.0, cy = c < n ? a.y[lo + c] : 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = lg + 4 * i;
+                double v;
+                if (r < n && c < n) {
+                    v = cov_pts(a.x[lo + r], a.y[lo + r], cx, cy, alpha, inv_beta, a.smooth) - acc[i];
+                    if (r == c) v += tau;
+                } else {
+                    v = (r == c) ? 1.0 : 0.0;
+                }
+                if (c <= r) Tw[r * LDT + c] = v;
+            }
+        }
+        wsync();
+        const bool bad = wave_potrf(Tw, LDT, 16);
+        if (bad && lane == 0) atomicCAS(a.status + th, 0, int(g + 1));
+        double ldv = (lane < n) ? log(Tw[lane * LDT + lane]) : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) ldv += __shfl_xor(ldv, off);
+        if (lane == 0) a.dval[th * a.d_stride + g] = 2.0 * ldv;
+        wave_trinv(Tw, LDT, Tiw, LDT, 16);
+        // z into its column, then F <- L^{-1} F tile by tile
+        if (lane < n) Fr[int64_t(lane) * a.WFs + (a.WF - 1)] = a.z[lo + lane];
+        wsync();
+        for (int c0 = 0; c0 < a.WF; c0 += 16) {
+            const int c = c0 + lr;
+            v4d o = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int kk = 4 * ks + lg;
+                const double bv = ldg0(Fr, int64_t(kk) * a.WFs + c, kk < n && c < a.WF);
+                o = mfma(Tiw[lr * LDT + kk], bv, o);
+            }
+            wsync();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = lg + 4 * i;
+                if (r < n && c < a.WF) Fr[int64_t(r) * a.WFs + c] = o[i];
+            }
+        }
+        wsync();
+    }
+}
+
+// Finest-level regions: S = C(S,S) - sum_l V^l V^l^T + tau I, its Cholesky
+// factor, d = log det S, and F <- L_S^{-1} [V^{M-1} .. V^1 | z] in place.
+// Leaves of up to 64 observations keep S in LDS.
+__global__ void __launch_bounds__(NT) k_leaf_finish(KArgs a) {
+    __shared__ Smem s;
+    __shared__ double Sl[TB * MLD];
+    const int64_t total = a.ntasks * a.ntheta;
+    const int M = a.M;
+    double* Sg = a.scratch + blockIdx.x * a.scratch_stride;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const int th = int(t / a.ntasks);
+        const int64_t g = a.tasks[t % a.ntasks];
+        const int64_t lo = a.obs_lo[g];
+        const int n = int(a.obs_hi[g] - lo);
+        const double* thp = a.theta + 3 * th;
+        const double alpha = thp[0], inv_beta = 1.0 / thp[1], tau = thp[2];
+        double* Frows = a.F + th * a.F_stride + lo * a.WFs;
+        const double* px = a.x + lo;
+        const double* py = a.y + lo;
+        double* S = (n <= TB) ? Sl : Sg;
+        const int64_t lds = (n <= TB) ? MLD : n;
+        for (int r = threadIdx.x; r < n; r += NT) Frows[int64_t(r) * a.WFs + (a.WF - 1)] = a.z[lo + r];
+        for (int64_t e0 = 0; e0 < int64_t(n) * n; e0 += 4 * NT) {
+            double xi[4], yi[4], xj[4], yj[4];
+#pragma unroll
+            for (int j2 = 0; j2 < 4; ++j2) {
+                const int64_t e = e0 + threadIdx.x + j2 * NT;
+                const bool ok = e < int64_t(n) * n;
+                const int i = ok ? int(e / n) : 0, j = ok ? int(e % n) : 0;
+                xi[j2] = px[i]; yi[j2] = py[i]; xj[j2] = px[j]; yj[j2] = py[j];
+            }
+#pragma unroll
+            for (int j2 = 0; j2 < 4; ++j2) {
+                const int64_t e = e0 + threadIdx.x + j2 * NT;
+                const int i = int(e / n), j = int(e % n);
+                if (e < int64_t(n) * n && j <= i) {
+                    double v = cov_pts(xi[j2], yi[j2], xj[j2], yj[j2], alpha, inv_beta, a.smooth);
+                    if (i == j) v += tau;
+                    S[i * lds + j] = v;
+                }
+            }
+        }
+        __syncthreads();
+        if (M > 1) wg_mm<MM_SUB>(S, lds, n, n, (M - 1) * a.P, Frows, a.WFs, 1, Frows, a.WFs, 1, true, s.mm);
         double logdet = 0.0;
-        if (wg_potrf_global(S, n, n, s.L, s.gemm, &s.flag, &logdet)) {
+        if (wg_potrf(S, lds, n, s.L, s.Li, s.mm, &s.flag, nullptr, &logdet)) {
             flag_fail(a, th, g);
             continue;
         }
         if (threadIdx.x == 0) a.dval[th * a.d_stride + g] = 2.0 * logdet;
-        wg_trsm_lln(S, n, n, Frows, a.WFs, a.WF, s.L, s.gemm);
+        wg_trsm_lln(S, lds, n, Frows, a.WFs, a.WF, s.L, s.Li, s.mm);
     }
 }
 
@@ -373,29 +723,32 @@ __global__ void __launch_bounds__(NT) k_leaf(KArgs a) {
 // this region's own knots), d = log det G, and F_rest <- L_G^{-1} F_rest.
 __global__ void __launch_bounds__(NT) k_fold_factor(KArgs a) {
     __shared__ Smem s;
+    __shared__ double Gl[TB * MLD];
     const int64_t total = a.ntasks * a.ntheta;
     const int m = a.level, P = a.P;
     const int cm = (a.M - 1 - m) * P;
-    double* G = a.scratch + blockIdx.x * a.scratch_stride;
+    double* Gg = a.scratch + blockIdx.x * a.scratch_stride;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         const int th = int(t / a.ntasks);
         const int64_t g = a.tasks[t % a.ntasks];
         const int64_t lo = a.obs_lo[g];
         const int n = int(a.obs_hi[g] - lo);
         double* Frows = a.F + th * a.F_stride + lo * a.WFs;
+        double* G = (n <= TB) ? Gl : Gg;
+        const int64_t ldg = (n <= TB) ? MLD : n;
         for (int64_t e = threadIdx.x; e < int64_t(n) * n; e += NT) {
             const int i = int(e / n), j = int(e % n);
-            if (j <= i) G[e] = (i == j) ? 1.0 : 0.0;
+            if (j <= i) G[i * ldg + j] = (i == j) ? 1.0 : 0.0;
         }
         __syncthreads();
-        wg_gemm<false>(G, n, n, n, P, Frows + cm, a.WFs, 1, Frows + cm, a.WFs, 1, true, s.gemm);
+        wg_mm<MM_ADD>(G, ldg, n, n, P, Frows + cm, a.WFs, 1, Frows + cm, a.WFs, 1, true, s.mm);
         double logdet = 0.0;
-        if (wg_potrf_global(G, n, n, s.L, s.gemm, &s.flag, &logdet)) {
+        if (wg_potrf(G, ldg, n, s.L, s.Li, s.mm, &s.flag, nullptr, &logdet)) {
             flag_fail(a, th, g);
             continue;
         }
         if (threadIdx.x == 0) a.dval[th * a.d_stride + g] = 2.0 * logdet;
-        wg_trsm_lln(G, n, n, Frows + cm + P, a.WFs, a.WF - cm - P, s.L, s.gemm);
+        wg_trsm_lln(G, ldg, n, Frows + cm + P, a.WFs, a.WF - cm - P, s.L, s.Li, s.mm);
     }
 }
 
@@ -424,36 +777,51 @@ __global__ void __launch_bounds__(NT) k_fold_gram(KArgs a) {
                 const int nc = int(a.obs_hi[gc] - lo);
                 if (nc == 0) continue;
                 const double* Fc = Fth + lo * a.WFs + cm;
-                wg_gemm<false>(G, D, D, D, nc, Fc, 1, a.WFs, Fc, 1, a.WFs, true, s.gemm);
+                wg_mm<MM_ADD>(G, D, D, D, nc, Fc, 1, a.WFs, Fc, 1, a.WFs, true, s.mm);
             } else {
                 const double* Gc = a.gram + th * a.gram_stride + a.gram_off[gc];
                 const int Dc = D + P;
-                for (int64_t e = threadIdx.x; e < int64_t(D) * D; e += NT) {
-                    const int i = int(e / D), jj = int(e % D);
-                    if (jj <= i) G[e] += Gc[int64_t(P + i) * Dc + P + jj];
+                const int64_t DD = int64_t(D) * D;
+                for (int64_t e0 = 0; e0 < DD; e0 += 8 * NT) {
+                    double gv[8], cv[8];
+#pragma unroll
+                    for (int j2 = 0; j2 < 8; ++j2) {
+                        const int64_t e = e0 + threadIdx.x + j2 * NT;
+                        const int i = int(e / D), jj = int(e % D);
+                        const bool ok = e < DD && jj <= i;
+                        gv[j2] = ldg0(G, e, ok);
+                        cv[j2] = ldg0(Gc, int64_t(P + i) * Dc + P + jj, ok);
+                    }
+#pragma unroll
+                    for (int j2 = 0; j2 < 8; ++j2) {
+                        const int64_t e = e0 + threadIdx.x + j2 * NT;
+                        const int i = int(e / D), jj = int(e % D);
+                        if (e < DD && jj <= i) G[e] = gv[j2] + cv[j2];
+                    }
                 }
                 __syncthreads();
             }
         }
-        // I + G_mm -> Cholesky in LDS
-        for (int e = threadIdx.x; e < P * P; e += NT) {
-            const int i = e / P, j = e % P;
-            s.L[i * (TB + 1) + j] = (j <= i) ? G[int64_t(i) * D + j] + (i == j ? 1.0 : 0.0) : 0.0;
+        // I + G_mm -> Cholesky and inverse in LDS
+        for (int e = threadIdx.x; e < TB * TB; e += NT) {
+            const int i = e / TB, j = e % TB;
+            s.L[i * MLD + j] = (i < P && j <= i) ? G[int64_t(i) * D + j] + (i == j ? 1.0 : 0.0) : 0.0;
         }
         __syncthreads();
-        if (wg_potrf_lds(s.L, P, TB + 1, &s.flag)) {
+        if (wg_potrf_lds(s.L, P, MLD, &s.flag)) {
             flag_fail(a, th, g);
             continue;
         }
         if (threadIdx.x == 0) {
             double ld = 0.0;
-            for (int i = 0; i < P; ++i) ld += log(s.L[i * (TB + 1) + i]);
+            for (int i = 0; i < P; ++i) ld += log(s.L[i * MLD + i]);
             a.dval[th * a.d_stride + g] = 2.0 * ld;
         }
+        wg_trinv_lds(s.L, MLD, s.Li, MLD, P);
         // Z = G[P:D, 0:P] <- Z L^{-T};  G[P:D, P:D] -= Z Z^T
         double* Z = G + int64_t(P) * D;
-        wg_trsm_rlt(Z, D, D - P, s.L, TB + 1, P);
-        wg_gemm<true>(Z + P, D, D - P, D - P, P, Z, D, 1, Z, D, 1, true, s.gemm);
+        wg_mm<MM_SET>(Z, D, D - P, P, P, Z, D, 1, s.Li, MLD, 1, false, s.mm);
+        wg_mm<MM_SUB>(Z + P, D, D - P, D - P, P, Z, D, 1, Z, D, 1, true, s.mm);
     }
 }
 
@@ -496,7 +864,10 @@ __global__ void __launch_bounds__(NT) k_final(KArgs a, int64_t nreg, int root_gr
     if (threadIdx.x == 0) {
         const double LOG2PI = 1.8378770664093454835606594728112;
         double ll = -0.5 * (a.n_used * LOG2PI + dsum + q);
-        if (a.status[th] != 0) ll = __builtin_nan("");
+        const double* thp = a.theta + 3 * th;
+        const bool ok = thp[0] > 0.0 && thp[1] > 0.0 && thp[2] > 0.0 && thp[0] < 1.0 / 0.0 && thp[1] < 1.0 / 0.0 &&
+                        thp[2] < 1.0 / 0.0;
+        if (a.status[th] != 0 || !ok) ll = __builtin_nan("");
         a.out[th] = ll;
     }
 }
@@ -513,12 +884,33 @@ __global__ void k_fill_int(int* p, int64_t n, int v) {
 
 // ------------------------------------------------------- host-side launchers
 
-hipError_t launch_prior(const KArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_prior, dim3(grid), dim3(NT), 0, st, a);
+int chain_lmax(int P) { (void)P; return MAXL - 1; }
+
+hipError_t launch_chain(const KArgs& a, int mode, int grid, hipStream_t st) {
+    switch (a.P) {
+        case 16: hipLaunchKernelGGL((k_chain<16>), dim3(grid), dim3(NT), 0, st, a, mode); break;
+        case 32: hipLaunchKernelGGL((k_chain<32>), dim3(grid), dim3(NT), 0, st, a, mode); break;
+        case 64: hipLaunchKernelGGL((k_chain<64>), dim3(grid), dim3(NT), 0, st, a, mode); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+hipError_t launch_prior_finish(const KArgs& a, int grid, hipStream_t st) {
+    const int g4 = (grid + 3) / 4;
+    switch (a.P) {
+        case 16: hipLaunchKernelGGL((k_prior_finish_w<16>), dim3(g4), dim3(NT), 0, st, a); break;
+        case 32: hipLaunchKernelGGL((k_prior_finish_w<32>), dim3(g4), dim3(NT), 0, st, a); break;
+        case 64: hipLaunchKernelGGL((k_prior_finish_w<64>), dim3(g4), dim3(NT), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+hipError_t launch_leaf_small(const KArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_leaf_small, dim3((grid + 3) / 4), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 hipError_t launch_leaf(const KArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_leaf, dim3(grid), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL(k_leaf_finish, dim3(grid), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 hipError_t launch_fold_factor(const KArgs& a, int grid, hipStream_t st) {
