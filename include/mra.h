@@ -137,7 +137,9 @@ int mra_tree_arrays(const mra_tree *tree, double *x, double *y, double *z, int64
 
 /*
  * Optional per-launch timing, for measurement.  While enabled, every kernel
- * launch of mra_loglik is bracketed by HIP events on the caller's stream.
+ * launch of mra_loglik is bracketed by HIP events on the caller's stream, or,
+ * with only_kernel non-NULL, only the launches of that kernel at only_level
+ * (the names mra_profile_read reports; MRA_EINVAL for an unknown name).
  * mra_profile_read waits for the recorded events, aggregates them by kernel
  * and level (elapsed milliseconds, launch count, and the algorithmic FP64
  * flops of what those launches computed, padding excluded), writes up to
@@ -152,7 +154,7 @@ typedef struct mra_kernel_stat {
     double flops;
 } mra_kernel_stat;
 
-int mra_profile_enable(int on);
+int mra_profile_enable(int on, const char *only_kernel, int only_level);
 int mra_profile_read(mra_kernel_stat *out, int cap, int *count);
 
 #ifdef __cplusplus

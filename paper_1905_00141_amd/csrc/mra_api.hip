@@ -20,7 +20,7 @@ int chain_lmax(int P);
 hipError_t launch_chain(const KArgs& a, int mode, int grid, hipStream_t st);
 hipError_t launch_prior_finish(const KArgs& a, int grid, hipStream_t st);
 hipError_t launch_leaf(const KArgs& a, int grid, hipStream_t st);
-hipError_t launch_leaf_small(const KArgs& a, int grid, hipStream_t st);
+hipError_t launch_small(const KArgs& a, int nmax, int mode, int grid, hipStream_t st);
 hipError_t launch_fold_factor(const KArgs& a, int grid, hipStream_t st);
 hipError_t launch_fold_gram(const KArgs& a, int grid, hipStream_t st);
 hipError_t launch_final(const KArgs& a, int64_t nreg, int root_gram, hipStream_t st);
@@ -84,23 +84,27 @@ struct mra_tree {
     int64_t vst_size = 0, gram_size = 0;
     int WF = 1, WFs = 2;
     std::vector<std::vector<int>> prior_tasks, factor_tasks, gram_tasks;  // index by level (1..M-1)
-    std::vector<int> leaf_tasks, small_tasks;  // leaves with > 16 / <= 16 observations
-    std::vector<int*> d_prior, d_factor, d_gramt;
+    std::vector<int> leaf_tasks;                     // leaves with > 64 observations
+    std::vector<int> small_tasks[3];                 // leaves with <= 16, 17..32, 33..64 observations
+    std::vector<std::vector<int>> fsmall_tasks[3];   // factor folds with <= 16, 17..32, 33..64 rows, by level
+    std::vector<int*> d_prior, d_factor, d_gramt, d_fsmall[3];
     int* d_leaf = nullptr;
-    int* d_small = nullptr;
+    int* d_small[3] = {nullptr, nullptr, nullptr};
     int64_t scratch_leaf = 0, scratch_fold = 0;  // doubles per workgroup slot
     int root_gram = 0;
     int64_t n_gram = 0, leaf_min = 0, leaf_max = 0;
     // algorithmic FP64 flops of one theta, per launch kind and level
     std::vector<double> fl_chain, fl_pfin, fl_factor, fl_gram;
-    double fl_leaf = 0.0, fl_small = 0.0;
+    double fl_leaf = 0.0, fl_small[3] = {0.0, 0.0, 0.0};
+    std::vector<double> fl_fsmall[3];
     void* ws = nullptr;  // Workspace*, owned
 
     ~mra_tree();
     void free_device() {
-        void* ps[] = {d_x, d_y, d_z, d_box, d_obs_lo, d_obs_hi, d_vst_off, d_gram_off, d_form, d_leaf, d_small};
+        void* ps[] = {d_x, d_y, d_z, d_box, d_obs_lo, d_obs_hi, d_vst_off, d_gram_off, d_form, d_leaf,
+                      d_small[0], d_small[1], d_small[2]};
         for (void* p : ps) if (p) (void)hipFree(p);
-        for (auto* v : {&d_prior, &d_factor, &d_gramt})
+        for (auto* v : {&d_prior, &d_factor, &d_gramt, &d_fsmall[0], &d_fsmall[1], &d_fsmall[2]})
             for (int* p : *v) if (p) (void)hipFree(p);
     }
 };
@@ -124,14 +128,18 @@ static void plan_flops(mra_tree& t) {
     t.fl_pfin.assign(M, 0.0);
     t.fl_factor.assign(M, 0.0);
     t.fl_gram.assign(M, 0.0);
+    for (int q = 0; q < 3; ++q) t.fl_fsmall[q].assign(M, 0.0);
     for (int m = 1; m < M; ++m) {
         const double nr = double(t.prior_tasks[m].size());
         t.fl_chain[m] = nr * p * p * p * double(m - 1) * (m - 1);
         t.fl_pfin[m] = nr * p * p * p * (double(m - 1) + 2.0 / 3.0);
-        for (int g : t.factor_tasks[m]) {
+        auto ff = [&](int g) {
             const double n = double(h.obs_hi[g] - h.obs_lo[g]);
-            t.fl_factor[m] += n * n * p + n * n * n / 3.0 + n * n * ((m - 1) * p + 1);
-        }
+            return n * n * p + n * n * n / 3.0 + n * n * ((m - 1) * p + 1);
+        };
+        for (int g : t.factor_tasks[m]) t.fl_factor[m] += ff(g);
+        for (int q = 0; q < 3; ++q)
+            for (int g : t.fsmall_tasks[q][m]) t.fl_fsmall[q][m] += ff(g);
         const double D = m * p + 1;
         for (int g : t.gram_tasks[m]) {
             const int64_t k = g - h.lvl_start[m - 1];
@@ -147,15 +155,14 @@ static void plan_flops(mra_tree& t) {
     }
     const double L = M - 1;
     t.fl_chain[M] = double(h.n_used) * p * p * L * L;
-    t.fl_leaf = t.fl_small = 0.0;
-    for (int g : t.leaf_tasks) {
+    auto fl = [&](int g) {
         const double n = double(h.obs_hi[g] - h.obs_lo[g]);
-        t.fl_leaf += L * n * n * p + n * n * n / 3.0 + n * n * (L * p + 1);
-    }
-    for (int g : t.small_tasks) {
-        const double n = double(h.obs_hi[g] - h.obs_lo[g]);
-        t.fl_small += L * n * n * p + n * n * n / 3.0 + n * n * (L * p + 1);
-    }
+        return L * n * n * p + n * n * n / 3.0 + n * n * (L * p + 1);
+    };
+    t.fl_leaf = t.fl_small[0] = t.fl_small[1] = t.fl_small[2] = 0.0;
+    for (int g : t.leaf_tasks) t.fl_leaf += fl(g);
+    for (int q = 0; q < 3; ++q)
+        for (int g : t.small_tasks[q]) t.fl_small[q] += fl(g);
 }
 
 // ---- optional per-launch timing (HIP events around every launch) ----------
@@ -167,9 +174,22 @@ struct ProfRec {
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+int g_prof_kind = -1, g_prof_level = -1;  // restrict to one (kernel, level); -1: all
 std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_event_pool;  // events are created once and reused
+
+hipEvent_t pooled_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
 const char* const KIND_NAMES[] = {"k_chain", "k_prior_finish", "k_leaf_finish", "k_fold_factor", "k_fold_gram",
-                                  "k_final", "k_leaf_small"};
+                                  "k_final", "k_small_leaf", "k_small_fold"};
 }  // namespace
 
 template <class F>
@@ -177,11 +197,16 @@ static hipError_t timed(int kind, int level, double flops, hipStream_t st, F&& l
     bool on;
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        on = g_prof_on;
+        on = g_prof_on && (g_prof_kind < 0 || (g_prof_kind == kind && g_prof_level == level));
     }
     if (!on) return launch();
     ProfRec r{kind, level, nullptr, nullptr, flops};
-    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return launch();
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        r.a = pooled_event();
+        r.b = pooled_event();
+    }
+    if (!r.a || !r.b) return launch();
     (void)hipEventRecord(r.a, st);
     const hipError_t e = launch();
     (void)hipEventRecord(r.b, st);
@@ -190,9 +215,17 @@ static hipError_t timed(int kind, int level, double flops, hipStream_t st, F&& l
     return e;
 }
 
-extern "C" int mra_profile_enable(int on) {
+extern "C" int mra_profile_enable(int on, const char* only_kernel, int only_level) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
+    g_prof_kind = -1;
+    g_prof_level = -1;
+    if (only_kernel) {
+        for (int k = 0; k < int(sizeof(KIND_NAMES) / sizeof(KIND_NAMES[0])); ++k)
+            if (std::strcmp(only_kernel, KIND_NAMES[k]) == 0) g_prof_kind = k;
+        if (g_prof_kind < 0) return fail(MRA_EINVAL, std::string("unknown kernel name ") + only_kernel);
+        g_prof_level = only_level;
+    }
     return MRA_OK;
 }
 
@@ -207,8 +240,11 @@ extern "C" int mra_profile_read(mra_kernel_stat* out, int cap, int* count) {
     for (ProfRec& r : recs) {
         float ms = 0.0f;
         if (hipEventSynchronize(r.b) == hipSuccess) (void)hipEventElapsedTime(&ms, r.a, r.b);
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
+        {
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            g_event_pool.push_back(r.a);
+            g_event_pool.push_back(r.b);
+        }
         mra_kernel_stat* s = nullptr;
         for (auto& x : agg)
             if (x.level == r.level && std::strcmp(x.name, KIND_NAMES[r.kind]) == 0) s = &x;
@@ -284,6 +320,7 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
     t->prior_tasks.assign(M, {});
     t->factor_tasks.assign(M, {});
     t->gram_tasks.assign(M, {});
+    for (int q = 0; q < 3; ++q) t->fsmall_tasks[q].assign(M, {});
     int64_t vo = 0, go = 0;
     for (int m = 1; m < M; ++m) {
         const int64_t thr = (flags & MRA_FOLD_GRAM) ? 0
@@ -298,7 +335,10 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
             vo += int64_t(m) * P * P;
             if (np <= thr) {
                 t->form[g] = FOLD_FACTOR;
-                t->factor_tasks[m].push_back(int(g));
+                if (np <= 16) t->fsmall_tasks[0][m].push_back(int(g));
+                else if (np <= 32) t->fsmall_tasks[1][m].push_back(int(g));
+                else if (np <= 64) t->fsmall_tasks[2][m].push_back(int(g));
+                else t->factor_tasks[m].push_back(int(g));
                 if (np > 64) t->scratch_fold = std::max(t->scratch_fold, np * np);
             } else {
                 t->form[g] = FOLD_GRAM;
@@ -316,11 +356,15 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
         const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
         t->leaf_min = std::min(t->leaf_min, nc);
         t->leaf_max = std::max(t->leaf_max, nc);
-        if (nc > 16) {
+        if (nc > 64) {
             t->leaf_tasks.push_back(int(g));
-            if (nc > 64) t->scratch_leaf = std::max(t->scratch_leaf, nc * nc);
+            t->scratch_leaf = std::max(t->scratch_leaf, nc * nc);
+        } else if (nc > 32) {
+            t->small_tasks[2].push_back(int(g));
+        } else if (nc > 16) {
+            t->small_tasks[1].push_back(int(g));
         } else if (nc > 0) {
-            t->small_tasks.push_back(int(g));
+            t->small_tasks[0].push_back(int(g));
         }
     }
     if (t->leaf_min == INT64_MAX) t->leaf_min = 0;
@@ -335,16 +379,20 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
         (rc = upload(&t->d_box, h.box)) || (rc = upload(&t->d_obs_lo, lo)) || (rc = upload(&t->d_obs_hi, hi)) ||
         (rc = upload(&t->d_vst_off, t->vst_off)) || (rc = upload(&t->d_gram_off, t->gram_off)) ||
         (rc = upload(&t->d_form, t->form)) || (rc = upload(&t->d_leaf, t->leaf_tasks)) ||
-        (rc = upload(&t->d_small, t->small_tasks))) {
+        (rc = upload(&t->d_small[0], t->small_tasks[0])) || (rc = upload(&t->d_small[1], t->small_tasks[1])) ||
+        (rc = upload(&t->d_small[2], t->small_tasks[2]))) {
         delete t;
         return fail(rc, "device allocation or copy failed while uploading the tree");
     }
     t->d_prior.assign(M, nullptr);
     t->d_factor.assign(M, nullptr);
     t->d_gramt.assign(M, nullptr);
+    for (int q = 0; q < 3; ++q) t->d_fsmall[q].assign(M, nullptr);
     for (int m = 1; m < M; ++m)
         if ((rc = upload(&t->d_prior[m], t->prior_tasks[m])) || (rc = upload(&t->d_factor[m], t->factor_tasks[m])) ||
-            (rc = upload(&t->d_gramt[m], t->gram_tasks[m]))) {
+            (rc = upload(&t->d_gramt[m], t->gram_tasks[m])) || (rc = upload(&t->d_fsmall[0][m], t->fsmall_tasks[0][m])) ||
+            (rc = upload(&t->d_fsmall[1][m], t->fsmall_tasks[1][m])) ||
+            (rc = upload(&t->d_fsmall[2][m], t->fsmall_tasks[2][m]))) {
             delete t;
             return fail(rc, "device allocation failed for task lists");
         }
@@ -406,6 +454,7 @@ struct Workspace {
     double *th = nullptr, *out = nullptr;
     int* status = nullptr;
     int64_t Bc = 0, nslot = 0, scratch_per = 0, cap_B = 0;
+    bool mem_limited = false;  // Bc was capped by device memory, not by the request
     hipEvent_t done = nullptr;
     hipStream_t last = nullptr;
     bool used = false;
@@ -431,7 +480,8 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
     const int64_t F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
     const int64_t per_theta = t->vst_size + F_stride + t->gram_size + h.nreg;
     const int64_t scratch_per = std::max<int64_t>({t->scratch_leaf, t->scratch_fold, 1});
-    if (w.Bc > 0 && (w.Bc >= B || w.Bc >= 64) && w.cap_B >= B) return MRA_OK;
+    // reuse when the buffers hold enough theta per chunk (or could not hold more)
+    if (w.Bc > 0 && w.cap_B >= B && (w.Bc >= B || w.mem_limited)) return MRA_OK;
     if (w.Bc > 0) {
         // grow: wait for the last user, release, reallocate
         w.release();
@@ -462,6 +512,7 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
         return fail(MRA_EDEVICE, "hipEventCreate failed");
     }
     w.Bc = Bc;
+    w.mem_limited = Bc < std::max<int64_t>(B, 1);
     w.nslot = nslot;
     w.scratch_per = scratch_per;
     w.cap_B = capB;
@@ -541,16 +592,28 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
             HIPCHK(timed(0, M, t->fl_chain[M] * nb, st, [&] { return launch_chain(a, 1, grid, st); }));
         }
         a.level = M;
-        a.tasks = t->d_small;
-        a.ntasks = int64_t(t->small_tasks.size());
-        if (a.ntasks > 0)
-            HIPCHK(timed(6, M, t->fl_small * nb, st, [&] { return launch_leaf_small(a, int(std::min<int64_t>(a.ntasks * nb, 1 << 18)), st); }));
+        for (int q = 0; q < 3; ++q) {
+            a.tasks = t->d_small[q];
+            a.ntasks = int64_t(t->small_tasks[q].size());
+            if (a.ntasks > 0)
+                HIPCHK(timed(6, M, t->fl_small[q] * nb, st, [&] {
+                    return launch_small(a, 16 << q, 0, int(std::min<int64_t>(a.ntasks * nb, 1 << 18)), st);
+                }));
+        }
         a.tasks = t->d_leaf;
         a.ntasks = int64_t(t->leaf_tasks.size());
         if (a.ntasks > 0)
             HIPCHK(timed(2, M, t->fl_leaf * nb, st, [&] { return launch_leaf(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st); }));
         for (int m = M - 1; m >= 1; --m) {
             a.level = m;
+            for (int q = 0; q < 3; ++q) {
+                a.tasks = t->d_fsmall[q][m];
+                a.ntasks = int64_t(t->fsmall_tasks[q][m].size());
+                if (a.ntasks > 0)
+                    HIPCHK(timed(7, m, t->fl_fsmall[q][m] * nb, st, [&] {
+                        return launch_small(a, 16 << q, 1, int(std::min<int64_t>(a.ntasks * nb, 1 << 18)), st);
+                    }));
+            }
             a.tasks = t->d_factor[m];
             a.ntasks = int64_t(t->factor_tasks[m].size());
             if (a.ntasks > 0)

@@ -103,90 +103,91 @@ __device__ __forceinline__ double ldg0(const double* p, int64_t off, bool ok) {
 
 // C(r,c) (+= | -= | =) sum_k A(r,k) B(c,k) over r < R, c < N (c <= r when
 // lower), A(r,k) = A[r*sar + k*sak], B(c,k) = B[c*sbc + k*sbk] (generic
-// pointers: global or LDS), C row-major (ldc).  64x64 output tiles: wave w
-// computes rows 16w..16w+15 with four 16x16 MFMA accumulators; K is staged
-// through LDS in chunks of 32, the next chunk's loads in flight (registers)
-// while the current one is multiplied.  With MM_SET an output tile may alias
-// the operand columns it is computed from (all reads precede its writes).
+// pointers: global or LDS), C row-major (ldc).  The output is cut into 64x64
+// blocks dealt round-robin to the workgroup's waves; a wave computes its block
+// with sixteen 16x16 MFMA accumulators, loading its A and B fragments straight
+// from memory (L1/L2; no LDS staging and no barrier inside), 16 values of k
+// per batch so that the loads of a batch are in flight together.  With MM_SET
+// an output block may alias the operand columns it is computed from (each
+// wave reads all of K for its block before writing it).  Ends with a
+// workgroup barrier.
 template <int MODE>
-__device__ __forceinline__ void wg_mm(double* C, int64_t ldc, int R, int N, int K, const double* A, int64_t sar, int64_t sak,
-                      const double* B, int64_t sbc, int64_t sbk, bool lower, double* sm) {
-    constexpr int EPT = TB * MK / NT;  // staged elements per thread and operand
-    double* As = sm;
-    double* Bs = sm + MK * MLD;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
-    const bool a_kfast = (sak == 1), b_kfast = (sbk == 1);
-    for (int r0 = 0; r0 < R; r0 += TB)
-        for (int c0 = 0; c0 < N; c0 += TB) {
-            if (lower && c0 > r0 + TB - 1) continue;
-            v4d acc[4];
+__device__ __forceinline__ void wg_mm(double* C, int64_t ldc, int R, int N, int K, const double* A, int64_t sar,
+                                      int64_t sak, const double* B, int64_t sbc, int64_t sbk, bool lower,
+                                      double* sm) {
+    (void)sm;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const int nbr = (R + TB - 1) / TB, nbc = (N + TB - 1) / TB;
+    for (int b = w; b < nbr * nbc; b += NT / 64) {
+        const int br = b / nbc, bc = b % nbc;
+        const int r0 = br * TB, c0 = bc * TB;
+        if (lower && c0 > r0 + TB - 1) continue;
+        v4d acc[4][4];
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) acc[ct] = v4d{0.0, 0.0, 0.0, 0.0};
-            // Thread tid stages elements e = tid + j*NT, j < EPT.  With k fastest
-            // (stride 1) they are (row tid/MK + j*NT/MK, k tid%MK), else
-            // (row tid%TB, k tid/TB + j*NT/TB): an arithmetic progression.
-            const int ar = a_kfast ? tid / MK : tid % TB, ak = a_kfast ? tid % MK : tid / TB;
-            const int br = b_kfast ? tid / MK : tid % TB, bk = b_kfast ? tid % MK : tid / TB;
-            const int adr = a_kfast ? NT / MK : 0, adk = a_kfast ? 0 : NT / TB;
-            const int bdr = b_kfast ? NT / MK : 0, bdk = b_kfast ? 0 : NT / TB;
-            double ra[EPT], rb[EPT];
-            auto fetch = [&](int k0) {
-                const double* pa = A + int64_t(r0 + ar) * sar + int64_t(k0 + ak) * sak;
-                const double* pb = B + int64_t(c0 + br) * sbc + int64_t(k0 + bk) * sbk;
-                const int64_t sa = int64_t(adr) * sar + int64_t(adk) * sak;
-                const int64_t sb = int64_t(bdr) * sbc + int64_t(bdk) * sbk;
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < EPT; ++j) {
-                    const bool oka = (r0 + ar + j * adr < R) && (k0 + ak + j * adk < K);
-                    const bool okb = (c0 + br + j * bdr < N) && (k0 + bk + j * bdk < K);
-                    const double va = *(oka ? pa + j * sa : A);
-                    const double vb = *(okb ? pb + j * sb : B);
-                    ra[j] = oka ? va : 0.0;
-                    rb[j] = okb ? vb : 0.0;
-                }
-            };
-            fetch(0);
-            for (int k0 = 0; k0 < K; k0 += MK) {
-                __syncthreads();
+            for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+        // per-lane row / column of each 16-row tile
+        bool rok[4], cok[4];
+        const double* pa[4];
+        const double* pb[4];
 #pragma unroll
-                for (int j = 0; j < EPT; ++j) {
-                    As[(ak + j * adk) * MLD + ar + j * adr] = ra[j];
-                    Bs[(bk + j * bdk) * MLD + br + j * bdr] = rb[j];
-                }
-                __syncthreads();
-                if (k0 + MK < K) fetch(k0 + MK);
+        for (int t = 0; t < 4; ++t) {
+            const int r = r0 + 16 * t + lr, c = c0 + 16 * t + lr;
+            rok[t] = r < R;
+            cok[t] = c < N;
+            pa[t] = A + (rok[t] ? int64_t(r) * sar : 0);
+            pb[t] = B + (cok[t] ? int64_t(c) * sbc : 0);
+        }
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            double fa[4][4], fb[4][4];  // [tile][k-step]
 #pragma unroll
-                for (int ks = 0; ks < MK / 4; ++ks) {
-                    const double av = As[(4 * ks + lg) * MLD + 16 * w + lr];
+            for (int q = 0; q < 4; ++q) {
+                const int k = k0 + 4 * q + lg;
+                const bool kok = k < K;
 #pragma unroll
-                    for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma(av, Bs[(4 * ks + lg) * MLD + 16 * ct + lr], acc[ct]);
+                for (int t = 0; t < 4; ++t) {
+                    const double va = *(rok[t] && kok ? pa[t] + int64_t(k) * sak : A);
+                    const double vb = *(cok[t] && kok ? pb[t] + int64_t(k) * sbk : B);
+                    fa[t][q] = (rok[t] && kok) ? va : 0.0;
+                    fb[t][q] = (cok[t] && kok) ? vb : 0.0;
                 }
             }
-            // epilogue: batch the reads of C before any write
-            double cold[16];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (!lower || c0 + 16 * j <= r0 + 16 * i + 15) acc[i][j] = mfma(fa[i][q], fb[j][q], acc[i][j]);
+        }
+        // epilogue, one 16-row strip at a time: reads of C batched before writes
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double cold[4][4];
             if (MODE != MM_SET) {
 #pragma unroll
-                for (int ct = 0; ct < 4; ++ct)
+                for (int j = 0; j < 4; ++j)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int r = r0 + 16 * w + lg + 4 * i, c = c0 + 16 * ct + lr;
-                        const bool ok = r < R && c < N && (!lower || c <= r);
-                        cold[4 * ct + i] = ldg0(C, int64_t(r) * ldc + c, ok);
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = r0 + 16 * i + lg + 4 * e, c = c0 + 16 * j + lr;
+                        cold[j][e] = ldg0(C, int64_t(r) * ldc + c, r < R && c < N && (!lower || c <= r));
                     }
             }
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = r0 + 16 * w + lg + 4 * i, c = c0 + 16 * ct + lr;
+                for (int e = 0; e < 4; ++e) {
+                    const int r = r0 + 16 * i + lg + 4 * e, c = c0 + 16 * j + lr;
                     if (r < R && c < N && (!lower || c <= r)) {
-                        double v = acc[ct][i];
-                        if (MODE == MM_ADD) v = cold[4 * ct + i] + v;
-                        else if (MODE == MM_SUB) v = cold[4 * ct + i] - v;
+                        double v = acc[i][j][e];
+                        if (MODE == MM_ADD) v = cold[j][e] + v;
+                        else if (MODE == MM_SUB) v = cold[j][e] - v;
                         C[int64_t(r) * ldc + c] = v;
                     }
                 }
         }
+    }
     __syncthreads();
 }
 
@@ -199,52 +200,94 @@ __device__ __forceinline__ void wsync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Cholesky of an n x n (n <= 64) lower triangle in LDS by one wave (lane r
-// owns row r).  Returns true on a non-positive pivot.
-__device__ __forceinline__ bool wave_potrf(double* T, int ld, int n) {
+// Value of v held by lane `src` (a compile-time constant after unrolling),
+// broadcast to the whole wave through two scalar reads.
+__device__ __forceinline__ double bcast(double v, int src) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(x), src);
+    const int hi = __builtin_amdgcn_readlane(int(x >> 32), src);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// L^{-1} of an existing n x n (n <= NMAX) lower-triangular factor L in LDS,
+// by one wave (lane j computes column j; rows of L broadcast from LDS).  Li
+// may be L itself (the inverse then replaces the factor).
+template <int NMAX>
+__device__ __forceinline__ void trinv_rows(const double* L, int ld, double* Li, int64_t ld2, int n) {
     const int lane = threadIdx.x & 63;
-    bool bad = false;
-    for (int j = 0; j < n; ++j) {
-        wsync();
-        double d = T[j * ld + j];
-        if (!(d > 0.0)) { bad = true; d = 1.0; }
-        d = sqrt(d);
-        wsync();
-        if (lane == j) T[j * ld + j] = d;
-        double lij = 0.0;
-        if (lane > j && lane < n) {
-            lij = T[lane * ld + j] / d;
-            T[lane * ld + j] = lij;
+    double x[NMAX];
+#pragma unroll
+    for (int q = 0; q < NMAX; ++q) {
+        if (q < n) {
+            double acc = (q == lane) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < q; ++k) acc = fma(-L[q * ld + k], x[k], acc);
+            x[q] = (q >= lane) ? acc / L[q * ld + q] : 0.0;
+        } else {
+            x[q] = 0.0;
         }
-        wsync();
-        if (lane > j && lane < n)
-            for (int k = j + 1; k <= lane; ++k) T[lane * ld + k] = fma(-lij, T[k * ld + j], T[lane * ld + k]);
     }
+    wsync();  // every read of L precedes the writes: Li may overwrite L
+    if (lane < n) {
+#pragma unroll
+        for (int q = 0; q < NMAX; ++q)
+            if (q < n) Li[int64_t(q) * ld2 + lane] = x[q];
+    }
+    wsync();
+}
+
+// Cholesky factor L of the n x n (n <= NMAX <= 64) lower triangle T (LDS, ld)
+// and, if Li is given, L^{-1} (generic pointer, ld2), by one wave.  Lane i
+// keeps row i in registers; column j of the factor is broadcast with scalar
+// lane reads, so the right-looking update makes no LDS round trips.  L
+// overwrites T (zero above the diagonal); Li receives the n x n lower
+// triangle and zeros above it.  Returns true (uniformly) on a non-positive
+// pivot.
+template <int NMAX>
+__device__ __forceinline__ bool wave_potrf_inv(double* T, int ld, double* Li, int64_t ld2, int n) {
+    const int lane = threadIdx.x & 63;
+    const int row = lane < NMAX ? lane : 0;
+    double r[NMAX];
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) {
+        const double v = T[row * ld + k];
+        r[k] = (lane < n && k <= lane) ? v : 0.0;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        if (j < n) {
+            const double piv = bcast(r[j], j);
+            bad = bad || !(piv > 0.0);
+            const double d = sqrt(piv > 0.0 ? piv : 1.0);
+            const double lij = (lane > j) ? r[j] / d : (lane == j ? d : 0.0);
+            r[j] = lij;
+#pragma unroll
+            for (int k = j + 1; k < NMAX; ++k)
+                if (k < n) r[k] = fma(-lij, bcast(lij, k), r[k]);
+        }
+    }
+    if (lane < n) {
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k)
+            if (k < n) T[lane * ld + k] = (k <= lane) ? r[k] : 0.0;
+    }
+    wsync();
+    // column `lane` of L^{-1}, rows of L read back from LDS (broadcast)
+    if (Li) trinv_rows<NMAX>(T, ld, Li, ld2, n);
     wsync();
     return bad;
 }
 
-// Li <- L^{-1} (n x n, n <= 64, lower) by one wave (lane j owns column j).
-__device__ __forceinline__ void wave_trinv(const double* L, int ld, double* Li, int64_t ld2, int n) {
-    const int j = threadIdx.x & 63;
-    for (int r = 0; r < n; ++r) {
-        if (j <= r) {
-            double s = (r == j) ? 1.0 : 0.0;
-            for (int k = j; k < r; ++k) s = fma(-L[r * ld + k], Li[k * ld2 + j], s);
-            Li[r * ld2 + j] = s / L[r * ld + r];
-        } else if (j < n) {
-            Li[r * ld2 + j] = 0.0;
-        }
-        wsync();
-    }
-}
-
-// In-place Cholesky of an n x n (n <= 64) lower triangle held in LDS (ld),
-// done by wave 0 while the others wait.  Returns true (in every thread) when
-// a pivot is not positive (the factor is then garbage).
-__device__ __forceinline__ bool wg_potrf_lds(double* T, int n, int ld, int* flag) {
+// Cholesky factor (in place) and inverse of an n x n (n <= 64) lower triangle
+// held in LDS, by wave 0 while the others wait.  Li (LDS, 64 x 64 tile)
+// receives L^{-1} padded with zeros.  Returns true in every thread when a
+// pivot is not positive (the factor is then garbage).
+__device__ __forceinline__ bool wg_potrf_inv_lds(double* T, int n, int ld, double* Li, int ld2, int* flag) {
+    for (int e = threadIdx.x; e < TB * TB; e += NT) Li[(e / TB) * ld2 + (e % TB)] = 0.0;
+    __syncthreads();
     if ((threadIdx.x >> 6) == 0) {
-        const bool bad = wave_potrf(T, ld, n);
+        const bool bad = wave_potrf_inv<TB>(T, ld, Li, ld2, n);
         if (threadIdx.x == 0) *flag = bad ? 1 : 0;
     }
     __syncthreads();
@@ -253,21 +296,20 @@ __device__ __forceinline__ bool wg_potrf_lds(double* T, int n, int ld, int* flag
     return bad;
 }
 
-// Li <- L^{-1} for an n x n (n <= 64) lower-triangular L in LDS (the rest of
-// the 64 x 64 tile of Li is zero), by wave 0.
-__device__ __forceinline__ void wg_trinv_lds(const double* L, int ld, double* Li, int ld2, int n) {
-    for (int e = threadIdx.x; e < TB * TB; e += NT) Li[(e / TB) * ld2 + (e % TB)] = 0.0;
-    __syncthreads();
-    if ((threadIdx.x >> 6) == 0) wave_trinv(L, ld, Li, ld2, n);
-    __syncthreads();
-}
-
-// Load an n x n lower triangle (global, ldg) into LDS (ld), zero elsewhere in
-// the 64 x 64 tile.
+// Load an n x n lower triangle (generic pointer, ldg) into LDS (ld), zero
+// elsewhere in the 64 x 64 tile.  All loads of a thread are issued first.
 __device__ __forceinline__ void load_tile(double* T, int ld, const double* G, int64_t ldg, int n) {
-    for (int e = threadIdx.x; e < TB * TB; e += NT) {
-        const int i = e / TB, j = e % TB;
-        T[i * ld + j] = (i < n && j <= i) ? G[int64_t(i) * ldg + j] : 0.0;
+    constexpr int PER = TB * TB / NT;
+    double v[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int e = threadIdx.x + j * NT, i = e / TB, c = e % TB;
+        v[j] = ldg0(G, int64_t(i) * ldg + c, i < n && c <= i);
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int e = threadIdx.x + j * NT;
+        T[(e / TB) * ld + (e % TB)] = v[j];
     }
     __syncthreads();
 }
@@ -283,19 +325,19 @@ __device__ __forceinline__ void store_tile(double* G, int64_t ldg, const double*
 // Blocked right-looking Cholesky of an n x n lower triangle (generic pointer,
 // lda).  Diagonal blocks are factored and inverted in LDS; panels are solved
 // as products with the inverted block.  *logdet (all threads) = sum log diag.
-__device__ __forceinline__ bool wg_potrf(double* A, int64_t lda, int n, double* Ls, double* Li, double* sm, int* flag,
-                         double* red, double* logdet) {
+// For n <= 64, Li holds L^{-1} on return.
+__device__ __forceinline__ bool wg_potrf(double* A, int64_t lda, int n, double* Ls, double* Li, double* sm,
+                                         int* flag, double* logdet) {
     double acc = 0.0;
     for (int j0 = 0; j0 < n; j0 += TB) {
         const int jb = min(TB, n - j0);
         double* Ajj = A + int64_t(j0) * lda + j0;
         load_tile(Ls, MLD, Ajj, lda, jb);
-        if (wg_potrf_lds(Ls, jb, MLD, flag)) return true;
+        if (wg_potrf_inv_lds(Ls, jb, MLD, Li, MLD, flag)) return true;
         store_tile(Ajj, lda, Ls, MLD, jb);
         for (int i = 0; i < jb; ++i) acc += log(Ls[i * MLD + i]);
         const int rest = n - j0 - jb;
         if (rest > 0) {
-            wg_trinv_lds(Ls, MLD, Li, MLD, jb);
             double* Aij = A + int64_t(j0 + jb) * lda + j0;
             // panel: A_ij <- A_ij L_jj^{-T}
             wg_mm<MM_SET>(Aij, lda, rest, jb, jb, Aij, lda, 1, Li, MLD, 1, false, sm);
@@ -304,19 +346,26 @@ __device__ __forceinline__ bool wg_potrf(double* A, int64_t lda, int n, double* 
                           true, sm);
         }
     }
-    (void)red;
     *logdet = acc;
     return false;
 }
 
 // X (n x W, ldx) <- L^{-1} X with L (n x n lower, generic pointer, ldl).
-// Diagonal blocks are inverted in LDS and applied as products.
-__device__ __forceinline__ void wg_trsm_lln(const double* L, int64_t ldl, int n, double* X, int64_t ldx, int W, double* Ls,
-                            double* Li, double* sm) {
+// Diagonal blocks are inverted in LDS and applied as products; with n <= 64
+// and have_inv the inverse already in Li is used.
+__device__ __forceinline__ void wg_trsm_lln(const double* L, int64_t ldl, int n, double* X, int64_t ldx, int W,
+                                            double* Ls, double* Li, double* sm, int* flag, bool have_inv) {
     for (int i0 = 0; i0 < n; i0 += TB) {
         const int ib = min(TB, n - i0);
-        load_tile(Ls, MLD, L + int64_t(i0) * ldl + i0, ldl, ib);
-        wg_trinv_lds(Ls, MLD, Li, MLD, ib);
+        if (!(have_inv && n <= TB)) {
+            load_tile(Ls, MLD, L + int64_t(i0) * ldl + i0, ldl, ib);
+            // the block is already a factor: its Cholesky factor is itself up to
+            // rounding of the diagonal; take the inverse of the stored factor
+            for (int e = threadIdx.x; e < TB * TB; e += NT) Li[(e / TB) * MLD + (e % TB)] = 0.0;
+            __syncthreads();
+            if ((threadIdx.x >> 6) == 0) trinv_rows<TB>(Ls, MLD, Li, MLD, ib);
+            __syncthreads();
+        }
         double* Xi = X + int64_t(i0) * ldx;
         // X_i <- Li X_i : C(r, c) = sum_k Li(r, k) X_i(k, c)
         wg_mm<MM_SET>(Xi, ldx, ib, W, ib, Li, MLD, 1, Xi, 1, ldx, false, sm);
@@ -325,6 +374,7 @@ __device__ __forceinline__ void wg_trsm_lln(const double* L, int64_t ldl, int n,
             wg_mm<MM_SUB>(X + int64_t(i0 + ib) * ldx, ldx, rest, W, ib, L + int64_t(i0 + ib) * ldl + i0, ldl, 1,
                           Xi, 1, ldx, false, sm);
     }
+    (void)flag;
 }
 
 // ------------------------------------------------------------------ kernels
@@ -580,26 +630,36 @@ __global__ void __launch_bounds__(NT) k_prior_finish_w(KArgs a) {
                 }
         }
         wsync();
-        if (wave_potrf(Tw, LDT, P) && lane == 0) atomicCAS(a.status + th, 0, int(g + 1));
-        // the inverse goes straight to its place (lane j writes and rereads column j)
-        wave_trinv(Tw, LDT, V + (m - 1) * P, ld, P);
-        wsync();
+        // factor in LDS; the inverse goes straight to its place in the V store
+        if (wave_potrf_inv<P>(Tw, LDT, V + (m - 1) * P, ld, P) && lane == 0) atomicCAS(a.status + th, 0, int(g + 1));
     }
 }
 
-// Finest-level regions with at most 16 observations, one wave per region:
-// S = C(S,S) - sum_l V^l V^l^T + tau I on the matrix cores (one 16x16 tile),
-// in-wave Cholesky, d = log det S, L^{-1}, and F <- L^{-1} [V | z] in
-// 16-column tiles.
-__global__ void __launch_bounds__(NT) k_leaf_small(KArgs a) {
-    constexpr int LDT = 17;
-    __shared__ double T[4][16 * LDT];
-    __shared__ double Ti[4][16 * LDT];
+// Small dense finisher, one wave per region of n <= NMAX rows (NMAX 16, 32 or
+// 64), on the matrix cores without workgroup barriers:
+//   FIN_LEAF (finest-level region): S = C(S,S) + tau I - V V^T with V the
+//     region's F rows, columns [0, (M-1)P); F <- L_S^{-1} [V | z] (all WF
+//     columns, z copied into the last one first); d = log det S.
+//   FIN_FOLD (observation-space fold at a.level): G = I + F_m F_m^T with F_m
+//     the columns of the region's own knots; F_rest <- L_G^{-1} F_rest;
+//     d = log det G.
+// The n x n matrix is padded to NMAX with an identity block; its inverse
+// factor replaces it in the wave's LDS tile.
+enum { FIN_LEAF = 0, FIN_FOLD = 1 };
+
+template <int NMAX, int MODE>
+__global__ void __launch_bounds__(NT) k_small(KArgs a) {
+    constexpr int LDT = NMAX + 1;
+    constexpr int NR = NMAX / 16;
+    __shared__ double T[4][NMAX * LDT];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
     const int64_t total = a.ntasks * a.ntheta;
-    const int M = a.M;
+    const int M = a.M, P = a.P;
     double* Tw = T[w];
-    double* Tiw = Ti[w];
+    double* Tiw = T[w];
+    const int kc0 = MODE == FIN_LEAF ? 0 : (M - 1 - a.level) * P;  // first column of the product
+    const int K = MODE == FIN_LEAF ? (M - 1) * P : P;
+    const int tc0 = MODE == FIN_LEAF ? 0 : kc0 + P;                  // first column of the solve
     for (int64_t t = int64_t(blockIdx.x) * 4 + w; t < total; t += int64_t(gridDim.x) * 4) {
         const int th = int(t / a.ntasks);
         const int64_t g = a.tasks[t % a.ntasks];
@@ -608,57 +668,89 @@ __global__ void __launch_bounds__(NT) k_leaf_small(KArgs a) {
         const double* thp = a.theta + 3 * th;
         const double alpha = thp[0], inv_beta = 1.0 / thp[1], tau = thp[2];
         double* Fr = a.F + th * a.F_stride + lo * a.WFs;
-        const int K = (M - 1) * a.P;
-        v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+        // product over K columns: 16x16 lower tiles (rt >= ct)
+        v4d acc[NR * (NR + 1) / 2];
+#pragma unroll
+        for (int e = 0; e < NR * (NR + 1) / 2; ++e) acc[e] = v4d{0.0, 0.0, 0.0, 0.0};
         for (int kb = 0; kb < K; kb += 16) {
-            v4d fr = v4d{0.0, 0.0, 0.0, 0.0};
-            if (lr < n) fr = *reinterpret_cast<const v4d*>(Fr + int64_t(lr) * a.WFs + kb + 4 * lg);
+            v4d fr[NR];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc = mfma(fr[j], fr[j], acc);
-        }
-        // S = C + tau I - acc (lower), identity beyond n
-        {
-            const int c = lr;
-            const double cx = c < n ? a.x[lo + c] : 0.0, cy = c < n ? a.y[lo + c] : 0.0;
+            for (int rt = 0; rt < NR; ++rt) {
+                const int row = 16 * rt + lr;
+                fr[rt] = v4d{0.0, 0.0, 0.0, 0.0};
+                if (row < n) fr[rt] = *reinterpret_cast<const v4d*>(Fr + int64_t(row) * a.WFs + kc0 + kb + 4 * lg);
+            }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = lg + 4 * i;
-                double v;
-                if (r < n && c < n) {
-                    v = cov_pts(a.x[lo + r], a.y[lo + r], cx, cy, alpha, inv_beta, a.smooth) - acc[i];
-                    if (r == c) v += tau;
-                } else {
-                    v = (r == c) ? 1.0 : 0.0;
-                }
-                if (c <= r) Tw[r * LDT + c] = v;
+            for (int j = 0; j < 4; ++j) {
+                int e = 0;
+#pragma unroll
+                for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+                    for (int ct = 0; ct <= rt; ++ct) acc[e] = mfma(fr[rt][j], fr[ct][j], acc[e]), ++e;
             }
         }
+        // matrix into LDS (lower), identity beyond n
+        {
+            int e = 0;
+#pragma unroll
+            for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+                for (int ct = 0; ct <= rt; ++ct) {
+                    const int c = 16 * ct + lr;
+                    double cx = 0.0, cy = 0.0;
+                    if (MODE == FIN_LEAF && c < n) { cx = a.x[lo + c]; cy = a.y[lo + c]; }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = 16 * rt + lg + 4 * i;
+                        double v;
+                        if (r < n && c < n) {
+                            if (MODE == FIN_LEAF) {
+                                v = cov_pts(a.x[lo + r], a.y[lo + r], cx, cy, alpha, inv_beta, a.smooth) - acc[e][i];
+                                if (r == c) v += tau;
+                            } else {
+                                v = acc[e][i] + (r == c ? 1.0 : 0.0);
+                            }
+                        } else {
+                            v = (r == c) ? 1.0 : 0.0;
+                        }
+                        if (c <= r) Tw[r * LDT + c] = v;
+                    }
+                    ++e;
+                }
+        }
         wsync();
-        const bool bad = wave_potrf(Tw, LDT, 16);
+        const bool bad = wave_potrf_inv<NMAX>(Tw, LDT, Tiw, LDT, NMAX);
         if (bad && lane == 0) atomicCAS(a.status + th, 0, int(g + 1));
-        double ldv = (lane < n) ? log(Tw[lane * LDT + lane]) : 0.0;
+        // the tile now holds L^{-1}: log det = -2 sum log diag(L^{-1})
+        double ldv = (lane < n) ? -log(Tw[lane * LDT + lane]) : 0.0;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) ldv += __shfl_xor(ldv, off);
         if (lane == 0) a.dval[th * a.d_stride + g] = 2.0 * ldv;
-        wave_trinv(Tw, LDT, Tiw, LDT, 16);
-        // z into its column, then F <- L^{-1} F tile by tile
-        if (lane < n) Fr[int64_t(lane) * a.WFs + (a.WF - 1)] = a.z[lo + lane];
-        wsync();
-        for (int c0 = 0; c0 < a.WF; c0 += 16) {
+        if (MODE == FIN_LEAF) {
+            if (lane < n) Fr[int64_t(lane) * a.WFs + (a.WF - 1)] = a.z[lo + lane];
+            wsync();
+        }
+        // solve: columns [tc0, WF) in 16-column tiles, Li (NMAX x NMAX) on the left
+        for (int c0 = tc0; c0 < a.WF; c0 += 16) {
             const int c = c0 + lr;
-            v4d o = v4d{0.0, 0.0, 0.0, 0.0};
+            v4d o[NR];
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
+            for (int rt = 0; rt < NR; ++rt) o[rt] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int ks = 0; ks < NMAX / 4; ++ks) {
                 const int kk = 4 * ks + lg;
                 const double bv = ldg0(Fr, int64_t(kk) * a.WFs + c, kk < n && c < a.WF);
-                o = mfma(Tiw[lr * LDT + kk], bv, o);
+#pragma unroll
+                for (int rt = 0; rt < NR; ++rt) o[rt] = mfma(Tiw[(16 * rt + lr) * LDT + kk], bv, o[rt]);
             }
             wsync();
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = lg + 4 * i;
-                if (r < n && c < a.WF) Fr[int64_t(r) * a.WFs + c] = o[i];
-            }
+            for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * rt + lg + 4 * i;
+                    if (r < n && c < a.WF) Fr[int64_t(r) * a.WFs + c] = o[rt][i];
+                }
         }
         wsync();
     }
@@ -709,12 +801,12 @@ __global__ void __launch_bounds__(NT) k_leaf_finish(KArgs a) {
         __syncthreads();
         if (M > 1) wg_mm<MM_SUB>(S, lds, n, n, (M - 1) * a.P, Frows, a.WFs, 1, Frows, a.WFs, 1, true, s.mm);
         double logdet = 0.0;
-        if (wg_potrf(S, lds, n, s.L, s.Li, s.mm, &s.flag, nullptr, &logdet)) {
+        if (wg_potrf(S, lds, n, s.L, s.Li, s.mm, &s.flag, &logdet)) {
             flag_fail(a, th, g);
             continue;
         }
         if (threadIdx.x == 0) a.dval[th * a.d_stride + g] = 2.0 * logdet;
-        wg_trsm_lln(S, lds, n, Frows, a.WFs, a.WF, s.L, s.Li, s.mm);
+        wg_trsm_lln(S, lds, n, Frows, a.WFs, a.WF, s.L, s.Li, s.mm, &s.flag, true);
     }
 }
 
@@ -743,12 +835,12 @@ __global__ void __launch_bounds__(NT) k_fold_factor(KArgs a) {
         __syncthreads();
         wg_mm<MM_ADD>(G, ldg, n, n, P, Frows + cm, a.WFs, 1, Frows + cm, a.WFs, 1, true, s.mm);
         double logdet = 0.0;
-        if (wg_potrf(G, ldg, n, s.L, s.Li, s.mm, &s.flag, nullptr, &logdet)) {
+        if (wg_potrf(G, ldg, n, s.L, s.Li, s.mm, &s.flag, &logdet)) {
             flag_fail(a, th, g);
             continue;
         }
         if (threadIdx.x == 0) a.dval[th * a.d_stride + g] = 2.0 * logdet;
-        wg_trsm_lln(G, ldg, n, Frows + cm + P, a.WFs, a.WF - cm - P, s.L, s.Li, s.mm);
+        wg_trsm_lln(G, ldg, n, Frows + cm + P, a.WFs, a.WF - cm - P, s.L, s.Li, s.mm, &s.flag, true);
     }
 }
 
@@ -808,7 +900,7 @@ __global__ void __launch_bounds__(NT) k_fold_gram(KArgs a) {
             s.L[i * MLD + j] = (i < P && j <= i) ? G[int64_t(i) * D + j] + (i == j ? 1.0 : 0.0) : 0.0;
         }
         __syncthreads();
-        if (wg_potrf_lds(s.L, P, MLD, &s.flag)) {
+        if (wg_potrf_inv_lds(s.L, P, MLD, s.Li, MLD, &s.flag)) {
             flag_fail(a, th, g);
             continue;
         }
@@ -817,7 +909,6 @@ __global__ void __launch_bounds__(NT) k_fold_gram(KArgs a) {
             for (int i = 0; i < P; ++i) ld += log(s.L[i * MLD + i]);
             a.dval[th * a.d_stride + g] = 2.0 * ld;
         }
-        wg_trinv_lds(s.L, MLD, s.Li, MLD, P);
         // Z = G[P:D, 0:P] <- Z L^{-T};  G[P:D, P:D] -= Z Z^T
         double* Z = G + int64_t(P) * D;
         wg_mm<MM_SET>(Z, D, D - P, P, P, Z, D, 1, s.Li, MLD, 1, false, s.mm);
@@ -905,8 +996,16 @@ hipError_t launch_prior_finish(const KArgs& a, int grid, hipStream_t st) {
     }
     return hipGetLastError();
 }
-hipError_t launch_leaf_small(const KArgs& a, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_leaf_small, dim3((grid + 3) / 4), dim3(NT), 0, st, a);
+// nmax: 16, 32 or 64; mode: FIN_LEAF or FIN_FOLD
+hipError_t launch_small(const KArgs& a, int nmax, int mode, int grid, hipStream_t st) {
+    const dim3 g((grid + 3) / 4);
+    if (nmax == 16 && mode == FIN_LEAF) hipLaunchKernelGGL((k_small<16, FIN_LEAF>), g, dim3(NT), 0, st, a);
+    else if (nmax == 32 && mode == FIN_LEAF) hipLaunchKernelGGL((k_small<32, FIN_LEAF>), g, dim3(NT), 0, st, a);
+    else if (nmax == 64 && mode == FIN_LEAF) hipLaunchKernelGGL((k_small<64, FIN_LEAF>), g, dim3(NT), 0, st, a);
+    else if (nmax == 16 && mode == FIN_FOLD) hipLaunchKernelGGL((k_small<16, FIN_FOLD>), g, dim3(NT), 0, st, a);
+    else if (nmax == 32 && mode == FIN_FOLD) hipLaunchKernelGGL((k_small<32, FIN_FOLD>), g, dim3(NT), 0, st, a);
+    else if (nmax == 64 && mode == FIN_FOLD) hipLaunchKernelGGL((k_small<64, FIN_FOLD>), g, dim3(NT), 0, st, a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 hipError_t launch_leaf(const KArgs& a, int grid, hipStream_t st) {

@@ -63,7 +63,7 @@ def load_library(path: str = LIB_PATH):
     L.mra_tree_info.restype = C.c_int
     L.mra_tree_arrays.argtypes = [vp, pd, pd, pd, pd, pd]
     L.mra_tree_arrays.restype = C.c_int
-    L.mra_profile_enable.argtypes = [C.c_int]
+    L.mra_profile_enable.argtypes = [C.c_int, C.c_char_p, C.c_int]
     L.mra_profile_enable.restype = C.c_int
     L.mra_profile_read.argtypes = [C.POINTER(KernelStat), C.c_int, C.POINTER(C.c_int)]
     L.mra_profile_read.restype = C.c_int
@@ -95,8 +95,10 @@ def _stream_ptr(stream):
     return int(getattr(stream, "cuda_stream", stream))
 
 
-def profile_enable(on: bool = True):
-    _check(_lib.mra_profile_enable(1 if on else 0))
+def profile_enable(on: bool = True, only_kernel: str | None = None, only_level: int = -1):
+    """Bracket launches of mra_loglik with HIP events (all, or one kernel at one level)."""
+    _check(_lib.mra_profile_enable(1 if on else 0, None if only_kernel is None else only_kernel.encode(),
+                                   only_level))
 
 
 def profile_read():
