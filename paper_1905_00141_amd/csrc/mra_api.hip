@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -40,8 +41,13 @@ int fail(int code, const std::string& msg) {
 }
 
 // Largest observation count a region may hold and still fold in observation
-// space (its scratch matrix is that count squared).
-constexpr int64_t FACTOR_FOLD_MAX = 512;
+// space (its scratch matrix is that count squared).  MRA_FACTOR_FOLD_MAX in
+// the environment overrides the default (for tuning).
+int64_t factor_fold_max() {
+    const char* e = std::getenv("MRA_FACTOR_FOLD_MAX");
+    if (e && *e) return std::max<int64_t>(0, std::atoll(e));
+    return 192;
+}
 
 struct DevBuf {
     void* p = nullptr;
@@ -325,7 +331,7 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
     for (int m = 1; m < M; ++m) {
         const int64_t thr = (flags & MRA_FOLD_GRAM) ? 0
                             : (flags & MRA_FOLD_FACTOR) ? 4096
-                            : std::min<int64_t>(int64_t(m - 1) * P + 1, FACTOR_FOLD_MAX);
+                            : std::min<int64_t>(int64_t(m - 1) * P + 1, factor_fold_max());
         const int64_t D = int64_t(m) * P + 1;
         for (int64_t g = h.lvl_start[m - 1]; g < h.lvl_start[m]; ++g) {
             const int64_t np = h.obs_hi[g] - h.obs_lo[g];

@@ -427,8 +427,8 @@ __device__ __forceinline__ void stage_block(double* blk, const double* src, int6
     }
 }
 
-template <int P>
-__global__ void __launch_bounds__(NT) k_chain(KArgs a, int mode) {
+template <int P, int mode>
+__global__ void __launch_bounds__(NT) k_chain(KArgs a) {
     constexpr int NM = P / 16;
     constexpr int GS = 256 / P;
     __shared__ double blk[P * (P + 1)];
@@ -977,11 +977,18 @@ __global__ void k_fill_int(int* p, int64_t n, int v) {
 
 int chain_lmax(int P) { (void)P; return MAXL - 1; }
 
+// mode 0: knots of the regions of a.level; mode 1: observations of the
+// level-(M-1) regions (a distinct kernel symbol, so that profilers report the
+// two separately)
 hipError_t launch_chain(const KArgs& a, int mode, int grid, hipStream_t st) {
-    switch (a.P) {
-        case 16: hipLaunchKernelGGL((k_chain<16>), dim3(grid), dim3(NT), 0, st, a, mode); break;
-        case 32: hipLaunchKernelGGL((k_chain<32>), dim3(grid), dim3(NT), 0, st, a, mode); break;
-        case 64: hipLaunchKernelGGL((k_chain<64>), dim3(grid), dim3(NT), 0, st, a, mode); break;
+    const int key = a.P * 2 + mode;
+    switch (key) {
+        case 32: hipLaunchKernelGGL((k_chain<16, 0>), dim3(grid), dim3(NT), 0, st, a); break;
+        case 33: hipLaunchKernelGGL((k_chain<16, 1>), dim3(grid), dim3(NT), 0, st, a); break;
+        case 64: hipLaunchKernelGGL((k_chain<32, 0>), dim3(grid), dim3(NT), 0, st, a); break;
+        case 65: hipLaunchKernelGGL((k_chain<32, 1>), dim3(grid), dim3(NT), 0, st, a); break;
+        case 128: hipLaunchKernelGGL((k_chain<64, 0>), dim3(grid), dim3(NT), 0, st, a); break;
+        case 129: hipLaunchKernelGGL((k_chain<64, 1>), dim3(grid), dim3(NT), 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
