@@ -367,6 +367,15 @@ typedef struct {
     double *kx, *ky;     /* knots */
 } anc_t;
 
+/* Prediction state, one entry per prediction point (points grouped by leaf):
+ * b = [b^1(p) .. b^{M-1}(p)] prior rows, H = [H^1 .. H^{M-1}], mu, v. */
+typedef struct {
+    int64_t n;
+    const double *x, *y;
+    const int64_t *leaf_off; /* nleaf + 1 */
+    double *b, *H, *mu, *v;
+} pred_t;
+
 typedef struct {
     const otree *t;
     cpar c;
@@ -375,6 +384,7 @@ typedef struct {
     double level_sum[O_MAXLEV];
     int status;
     int64_t bad_region;
+    pred_t *pred;            /* NULL for the likelihood */
 } rctx;
 
 /* B^l(P) for l = 1..Lc, with Z^l = B^l K_{A_l} for l = 1..Lc (Z needed for l < Lc
@@ -457,6 +467,109 @@ static void free_region(rctx *ctx, int m) {
     memset(me, 0, sizeof *me);
 }
 
+/* Kriging at the finest level (prediction, Sec. 2.2; a point joins the
+ * finest-level set of its leaf, so the remainder C_M is used exactly).  For a
+ * point p of leaf R with observations S (np of them, Sigma = C_M(S,S) + tau I
+ * factored in S_chol, B^l the observations' prior rows):
+ *   G = C_M(p, S) = C(p,S) - sum_i b^i(p) K_{A_i} B^i^T,
+ *   mu = G Sigma^{-1} z,  H^k = G Sigma^{-1} B^k,
+ *   v = C_M(p,p) - G Sigma^{-1} G^T,  C_M(p,p) = C(p,p) - sum_i b^i K_{A_i} b^i^T. */
+static void leaf_predict(rctx *ctx, int64_t k, int64_t np, const double *sx, const double *sy, const double *sz,
+                         double **B, const double *S_chol) {
+    const otree *t = ctx->t;
+    pred_t *pr = ctx->pred;
+    int p = ctx->p, M = t->M;
+    int64_t po = pr->leaf_off[k], pn = pr->leaf_off[k + 1] - po;
+    if (pn == 0) return;
+    int q = (M - 1) * p;
+    const double *qx = pr->x + po, *qy = pr->y + po;
+    double *Bp[O_MAXLEV + 1] = {0}, *Zp[O_MAXLEV + 1] = {0};
+    for (int l = 1; l < M; l++) {
+        Bp[l] = malloc(sizeof(double) * pn * p);
+        Zp[l] = malloc(sizeof(double) * pn * p);
+    }
+    prior_rows(ctx, (int)pn, qx, qy, M - 1, Bp, Zp);
+    for (int64_t j = 0; j < pn; j++) {
+        double *bj = pr->b + (po + j) * (q > 0 ? q : 1);
+        for (int l = 1; l < M; l++)
+            for (int c = 0; c < p; c++) bj[(l - 1) * p + c] = Bp[l][j * p + c];
+        double cmpp = cov(qx[j], qy[j], qx[j], qy[j], &ctx->c);
+        for (int i = 1; i < M; i++)
+            for (int c = 0; c < p; c++) cmpp -= Zp[i][j * p + c] * Bp[i][j * p + c];
+        pr->mu[po + j] = 0.0;
+        pr->v[po + j] = cmpp;
+        double *Hj = pr->H + (po + j) * (q > 0 ? q : 1);
+        for (int e = 0; e < q; e++) Hj[e] = 0.0;
+    }
+    if (np > 0) {
+        /* Y = Sigma^{-1} G^T  (np x pn) */
+        double *G = malloc(sizeof(double) * pn * np);
+        double *Y = malloc(sizeof(double) * np * pn);
+        for (int64_t j = 0; j < pn; j++)
+            for (int64_t a = 0; a < np; a++) {
+                double g = cov(qx[j], qy[j], sx[a], sy[a], &ctx->c);
+                for (int i = 1; i < M; i++)
+                    for (int c = 0; c < p; c++) g -= Zp[i][j * p + c] * B[i][a * p + c];
+                G[j * np + a] = g;
+                Y[a * pn + j] = g;
+            }
+        chol_solve(S_chol, (int)np, Y, (int)pn);
+        for (int64_t j = 0; j < pn; j++) {
+            double mu = 0.0, gy = 0.0;
+            for (int64_t a = 0; a < np; a++) {
+                mu += Y[a * pn + j] * sz[a];
+                gy += G[j * np + a] * Y[a * pn + j];
+            }
+            pr->mu[po + j] = mu;
+            pr->v[po + j] -= gy;
+            double *Hj = pr->H + (po + j) * q;
+            for (int l = 1; l < M; l++)
+                for (int c = 0; c < p; c++) {
+                    double h = 0.0;
+                    for (int64_t a = 0; a < np; a++) h += Y[a * pn + j] * B[l][a * p + c];
+                    Hj[(l - 1) * p + c] = h;
+                }
+        }
+        free(G); free(Y);
+    }
+    for (int l = 1; l < M; l++) { free(Bp[l]); free(Zp[l]); }
+}
+
+/* Fold of the prediction state at region k of level m (after its posterior
+ * Kt^{-1} = B^m_R + At^{mm} is factored in Ki): for every prediction point of
+ * the subtree, E = b^m(p) - H^m, u = Kt E^T,
+ *   mu += u . wt^m,  H^k += u^T At^{m,k} (k < m),  v += E u. */
+static void fold_predict(rctx *ctx, int m, int64_t k, const double *Ki, const double *At, const double *wt) {
+    const otree *t = ctx->t;
+    pred_t *pr = ctx->pred;
+    int p = ctx->p, M = t->M;
+    int64_t span = 1;
+    for (int e = 0; e < M - m; e++) span *= t->J;
+    int64_t lo = pr->leaf_off[k * span], hi = pr->leaf_off[(k + 1) * span];
+    int q = m * p, qq = (M - 1) * p, o = (m - 1) * p;
+    double *E = malloc(sizeof(double) * p);
+    for (int64_t j = lo; j < hi; j++) {
+        const double *bj = pr->b + j * qq;
+        double *Hj = pr->H + j * qq;
+        for (int a = 0; a < p; a++) E[a] = bj[(m - 1) * p + a] - Hj[(m - 1) * p + a];
+        double *u = malloc(sizeof(double) * p);
+        memcpy(u, E, sizeof(double) * p);
+        chol_solve(Ki, p, u, 1);
+        double dm = 0.0, dv = 0.0;
+        for (int a = 0; a < p; a++) { dm += u[a] * wt[o + a]; dv += E[a] * u[a]; }
+        pr->mu[j] += dm;
+        pr->v[j] += dv;
+        for (int kk = 1; kk < m; kk++)
+            for (int c = 0; c < p; c++) {
+                double h = 0.0;
+                for (int a = 0; a < p; a++) h += u[a] * At[(int64_t)(o + a) * q + (kk - 1) * p + c];
+                Hj[(kk - 1) * p + c] += h;
+            }
+        free(u);
+    }
+    free(E);
+}
+
 /* Visit region k at level m (1-based).  On return, A (size (m-1)p square,
  * full), w ((m-1)p) hold the region's statistics for its ancestors 1..m-1, and
  * *du the sum of d+u over the subtree. */
@@ -471,7 +584,10 @@ static void visit(rctx *ctx, int m, int64_t k, double *A, double *w, double *du)
         int q = (M - 1) * p;
         memset(A, 0, sizeof(double) * (size_t)q * q);
         memset(w, 0, sizeof(double) * (size_t)(q > 0 ? q : 1));
-        if (np == 0) return;
+        if (np == 0) {
+            if (ctx->pred) leaf_predict(ctx, k, 0, NULL, NULL, NULL, NULL, NULL);
+            return;
+        }
         const double *px = t->x + o, *py = t->y + o, *pz = t->z + o;
         double *B[O_MAXLEV + 1] = {0}, *Z[O_MAXLEV + 1] = {0};
         for (int l = 1; l < M; l++) {
@@ -525,6 +641,7 @@ static void visit(rctx *ctx, int m, int64_t k, double *A, double *w, double *du)
         *du = d + u;
         ctx->level_sum[M - 1] += d + u;
         free(X);
+        if (ctx->pred) leaf_predict(ctx, k, np, px, py, pz, B, S);
     leaf_done:
         free(S);
         for (int l = 1; l < M; l++) { free(B[l]); free(Z[l]); }
@@ -563,6 +680,7 @@ static void visit(rctx *ctx, int m, int64_t k, double *A, double *w, double *du)
         if (chol(Ki, p)) {
             ctx->status = O_ENOTPD; ctx->bad_region = t->lvl_start[m - 1] + k;
         } else {
+            if (ctx->pred) fold_predict(ctx, m, k, Ki, At, wt);
             double d = logdet_chol(Ki, p) - logdet_chol(me->L, p);
             /* Y = Kt [At^{m,1..m-1} | wt^m]  (p x ((m-1)p + 1)) */
             int qo = (m - 1) * p, wd = qo + 1;
@@ -671,16 +789,25 @@ int oracle_mra_loglik(const otree *t, int family, double nu, const double *theta
 /*   Finally the leaf remainder C_M(a,b) is added for a, b in the same leaf.  */
 /* ------------------------------------------------------------------------ */
 
-/* Sigma_MRA over the used observations (n_used x n_used, sorted order). */
-int oracle_dense_sigma(const otree *t, int family, double nu, const double *theta, double *Sig) {
-    cpar c;
-    int rc = make_par(family, nu, theta, &c);
-    if (rc) return rc;
-    int64_t n = t->n_used;
+/* Leaf of a location by descent from the root (half-open regions). */
+static int locate_leaf(const otree *t, double x, double y, int64_t *leaf) {
+    const double *rb = t->box;
+    if (!(x >= rb[0] && x < rb[1] && y >= rb[2] && y < rb[3])) return O_EDOMAIN;
+    int64_t k = 0;
+    for (int m = 0; m + 1 < t->M; m++) k = t->J * k + child_of(t->box + 4 * (t->lvl_start[m] + k), t->J, x, y);
+    *leaf = k;
+    return O_OK;
+}
+
+/* Sigma_MRA over the used observations followed by ne extra finest-level
+ * points (ex, ey in leaves eleaf): (n + ne) x (n + ne). */
+static int dense_sigma_ext(const otree *t, const cpar *c, int64_t ne, const double *ex, const double *ey,
+                           const int64_t *eleaf, double *Sig) {
+    int64_t n = t->n_used, nn = n + ne;
     int p = t->rhat, M = t->M, J = t->J;
     int64_t nk = 0;
     for (int m = 1; m < M; m++) nk += ipow(J, m - 1) * p;
-    int64_t nU = n + nk;
+    int64_t nU = nn + nk;
     if (nU > 12000) return fail(O_EINVAL, "dense path limited to 12000 points");
     double *ux = malloc(sizeof(double) * nU), *uy = malloc(sizeof(double) * nU);
     int *lev = malloc(sizeof(int) * nU);
@@ -690,13 +817,18 @@ int oracle_dense_sigma(const otree *t, int family, double nu, const double *thet
         free(ux); free(uy); free(lev); free(reg); free(C);
         return fail(O_ENOMEM, "oom");
     }
-    /* observations first (indices 0..n-1), then knots level by level */
+    /* observations (indices 0..n-1), extra points (n..nn-1), then knots level by level */
     for (int64_t k = 0; k < t->nleaf; k++)
         for (int64_t a = t->leaf_off[k]; a < t->leaf_off[k + 1]; a++) {
             ux[a] = t->x[a]; uy[a] = t->y[a]; lev[a] = M;
             for (int l = 1; l <= M; l++) reg[a * (M + 1) + l] = k / ipow(J, M - l);
         }
-    int64_t u = n;
+    for (int64_t e = 0; e < ne; e++) {
+        int64_t a = n + e;
+        ux[a] = ex[e]; uy[a] = ey[e]; lev[a] = M;
+        for (int l = 1; l <= M; l++) reg[a * (M + 1) + l] = eleaf[e] / ipow(J, M - l);
+    }
+    int64_t u = nn;
     for (int m = 1; m < M; m++)
         for (int64_t k = 0; k < ipow(J, m - 1); k++) {
             const double *b = t->box + 4 * (t->lvl_start[m - 1] + k);
@@ -707,14 +839,14 @@ int oracle_dense_sigma(const otree *t, int family, double nu, const double *thet
             }
         }
     for (int64_t a = 0; a < nU; a++)
-        for (int64_t b = 0; b < nU; b++) C[a * nU + b] = cov(ux[a], uy[a], ux[b], uy[b], &c);
-    memset(Sig, 0, sizeof(double) * n * n);
+        for (int64_t b = 0; b < nU; b++) C[a * nU + b] = cov(ux[a], uy[a], ux[b], uy[b], c);
+    memset(Sig, 0, sizeof(double) * nn * nn);
 
     int64_t *P = malloc(sizeof(int64_t) * (nU > 0 ? nU : 1));
     int64_t *Qi = malloc(sizeof(int64_t) * p);
     double *G = malloc(sizeof(double) * p * p);
     int status = O_OK;
-    int64_t kstart = n;
+    int64_t kstart = nn;
     for (int m = 1; m < M && !status; m++) {
         int64_t nreg_m = ipow(J, m - 1);
         for (int64_t k = 0; k < nreg_m && !status; k++) {
@@ -736,7 +868,7 @@ int oracle_dense_sigma(const otree *t, int family, double nu, const double *thet
                     int64_t ia = P[a], ib = P[b];
                     double s = 0.0;
                     for (int i = 0; i < p; i++) s += C[ia * nU + Qi[i]] * X[i * np + b];
-                    if (ia < n && ib < n) Sig[ia * n + ib] += s;
+                    if (ia < nn && ib < nn) Sig[ia * nn + ib] += s;
                     if (reg[ia * (M + 1) + m + 1] == reg[ib * (M + 1) + m + 1])
                         C[ia * nU + ib] -= s; /* becomes C_{m+1} */
                     else
@@ -747,14 +879,22 @@ int oracle_dense_sigma(const otree *t, int family, double nu, const double *thet
         kstart += nreg_m * p;
     }
     if (!status) {
-        for (int64_t a = 0; a < n; a++)
-            for (int64_t b = 0; b < n; b++)
-                if (reg[a * (M + 1) + M] == reg[b * (M + 1) + M]) Sig[a * n + b] += C[a * nU + b];
+        for (int64_t a = 0; a < nn; a++)
+            for (int64_t b = 0; b < nn; b++)
+                if (reg[a * (M + 1) + M] == reg[b * (M + 1) + M]) Sig[a * nn + b] += C[a * nU + b];
     }
     free(P); free(Qi); free(G);
     free(ux); free(uy); free(lev); free(reg); free(C);
     if (status) return fail(status, "dense path: knot covariance not positive definite");
     return O_OK;
+}
+
+/* Sigma_MRA over the used observations (n_used x n_used, sorted order). */
+int oracle_dense_sigma(const otree *t, int family, double nu, const double *theta, double *Sig) {
+    cpar c;
+    int rc = make_par(family, nu, theta, &c);
+    if (rc) return rc;
+    return dense_sigma_ext(t, &c, 0, NULL, NULL, NULL, Sig);
 }
 
 /* Gaussian log-density of z under S + tau I (S is n x n, overwritten). */
@@ -799,5 +939,122 @@ int oracle_exact_loglik(const otree *t, int family, double nu, const double *the
         for (int64_t b = 0; b < n; b++) S[a * n + b] = cov(t->x[a], t->y[a], t->x[b], t->y[b], &c);
     rc = gauss_loglik(S, t->z, n, c.tau, out);
     free(S);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Prediction (kriging) of the latent process X at np locations given the    */
+/* data (prediction mode, Sec. 2.2): posterior mean and variance.            */
+/* ------------------------------------------------------------------------ */
+
+static int sort_points(const otree *t, const double *px, const double *py, int64_t np, double **sx, double **sy,
+                       int64_t **perm, int64_t **off, int64_t **leafs) {
+    int64_t *leaf = malloc(sizeof(int64_t) * (np > 0 ? np : 1));
+    for (int64_t i = 0; i < np; i++)
+        if (locate_leaf(t, px[i], py[i], &leaf[i])) {
+            free(leaf);
+            return fail(O_EDOMAIN, "prediction location outside the root region");
+        }
+    int64_t *cnt = calloc(t->nleaf + 1, sizeof(int64_t));
+    for (int64_t i = 0; i < np; i++) cnt[leaf[i] + 1]++;
+    for (int64_t k = 0; k < t->nleaf; k++) cnt[k + 1] += cnt[k];
+    int64_t *fill = malloc(sizeof(int64_t) * (t->nleaf > 0 ? t->nleaf : 1));
+    memcpy(fill, cnt, sizeof(int64_t) * t->nleaf);
+    *sx = malloc(sizeof(double) * (np > 0 ? np : 1));
+    *sy = malloc(sizeof(double) * (np > 0 ? np : 1));
+    *perm = malloc(sizeof(int64_t) * (np > 0 ? np : 1));
+    for (int64_t i = 0; i < np; i++) {
+        int64_t d = fill[leaf[i]]++;
+        (*sx)[d] = px[i]; (*sy)[d] = py[i]; (*perm)[d] = i;
+    }
+    free(fill);
+    *off = cnt;
+    *leafs = leaf;
+    return O_OK;
+}
+
+/* The recursion: leaf kriging, then the fold updates of mu, H, v. */
+int oracle_mra_predict(const otree *t, int family, double nu, const double *theta, const double *px,
+                       const double *py, int64_t np, double *mean, double *var) {
+    cpar c;
+    int rc = make_par(family, nu, theta, &c);
+    if (rc) return rc;
+    if (!(c.tau > 0.0)) return fail(O_EINVAL, "tau must be positive");
+    double *sx, *sy;
+    int64_t *perm, *off, *leaf;
+    rc = sort_points(t, px, py, np, &sx, &sy, &perm, &off, &leaf);
+    if (rc) return rc;
+    int q = (t->M - 1) * t->rhat;
+    pred_t pr = {np, sx, sy, off, NULL, NULL, NULL, NULL};
+    size_t w = (size_t)(q > 0 ? q : 1) * (size_t)(np > 0 ? np : 1);
+    pr.b = calloc(w, sizeof(double));
+    pr.H = calloc(w, sizeof(double));
+    pr.mu = calloc(np > 0 ? np : 1, sizeof(double));
+    pr.v = calloc(np > 0 ? np : 1, sizeof(double));
+    rctx *ctx = calloc(1, sizeof *ctx);
+    ctx->t = t;
+    ctx->p = t->rhat;
+    ctx->c = c;
+    ctx->pred = &pr;
+    double dA[1], dw[1], du = 0.0;
+    visit(ctx, 1, 0, dA, dw, &du);
+    rc = ctx->status ? fail(O_ENOTPD, "not positive definite") : O_OK;
+    if (!rc)
+        for (int64_t d = 0; d < np; d++) {
+            mean[perm[d]] = pr.mu[d];
+            var[perm[d]] = pr.v[d];
+        }
+    free(ctx);
+    free(pr.b); free(pr.H); free(pr.mu); free(pr.v);
+    free(sx); free(sy); free(perm); free(off); free(leaf);
+    return rc;
+}
+
+/* The definition: with the prediction points joined to the finest level,
+ * mean = Sigma(p,S) (Sigma(S,S) + tau I)^{-1} z and
+ * var = Sigma(p,p) - Sigma(p,S) (Sigma(S,S) + tau I)^{-1} Sigma(S,p). */
+int oracle_dense_predict(const otree *t, int family, double nu, const double *theta, const double *px,
+                         const double *py, int64_t np, double *mean, double *var) {
+    cpar c;
+    int rc = make_par(family, nu, theta, &c);
+    if (rc) return rc;
+    int64_t *leaf = malloc(sizeof(int64_t) * (np > 0 ? np : 1));
+    for (int64_t i = 0; i < np; i++)
+        if (locate_leaf(t, px[i], py[i], &leaf[i])) {
+            free(leaf);
+            return fail(O_EDOMAIN, "prediction location outside the root region");
+        }
+    int64_t n = t->n_used, nn = n + np;
+    double *S = malloc(sizeof(double) * nn * nn);
+    rc = dense_sigma_ext(t, &c, np, px, py, leaf, S);
+    if (!rc) {
+        /* K = Sigma(S,S) + tau I, factor; solve K X = [Sigma(S,p) | z] */
+        double *K = malloc(sizeof(double) * n * n);
+        for (int64_t a = 0; a < n; a++)
+            for (int64_t b = 0; b < n; b++) K[a * n + b] = S[a * nn + b] + (a == b ? c.tau : 0.0);
+        if (chol(K, (int)n)) {
+            rc = fail(O_ENOTPD, "dense covariance not positive definite");
+        } else {
+            int64_t wd = np + 1;
+            double *X = malloc(sizeof(double) * n * wd);
+            for (int64_t a = 0; a < n; a++) {
+                for (int64_t j = 0; j < np; j++) X[a * wd + j] = S[a * nn + n + j];
+                X[a * wd + np] = t->z[a];
+            }
+            chol_solve(K, (int)n, X, (int)wd);
+            for (int64_t j = 0; j < np; j++) {
+                double mu = 0.0, g = 0.0;
+                for (int64_t a = 0; a < n; a++) {
+                    mu += S[(n + j) * nn + a] * X[a * wd + np];
+                    g += S[(n + j) * nn + a] * X[a * wd + j];
+                }
+                mean[j] = mu;
+                var[j] = S[(n + j) * nn + n + j] - g;
+            }
+            free(X);
+        }
+        free(K);
+    }
+    free(S); free(leaf);
     return rc;
 }
