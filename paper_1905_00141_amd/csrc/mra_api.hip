@@ -1,5 +1,6 @@
-// C-ABI entry points of the MRA library: tree upload, execution plan,
-// memory sizing and the per-level launch schedule.
+// C-ABI entry points of the MRA library: tree upload, execution plans,
+// device workspace, the per-level launch schedule, graph capture of repeated
+// evaluations, and kriging.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -8,8 +9,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/mra.h"
@@ -25,6 +28,9 @@ hipError_t launch_small(const KArgs& a, int nmax, int mode, int grid, hipStream_
 hipError_t launch_fold_factor(const KArgs& a, int grid, hipStream_t st);
 hipError_t launch_fold_gram(const KArgs& a, int grid, hipStream_t st);
 hipError_t launch_final(const KArgs& a, int64_t nreg, int root_gram, hipStream_t st);
+hipError_t launch_pred_leaf(const KArgs& a, int grid, hipStream_t st);
+hipError_t launch_pred_fold(const KArgs& a, hipStream_t st);
+hipError_t launch_pred_out(const KArgs& a, hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st);
 }  // namespace mra
@@ -49,11 +55,6 @@ int64_t factor_fold_max() {
     return 192;
 }
 
-struct DevBuf {
-    void* p = nullptr;
-    ~DevBuf() { if (p) (void)hipFree(p); }
-};
-
 template <class T>
 int upload(T** dst, const std::vector<T>& v) {
     *dst = nullptr;
@@ -74,45 +75,60 @@ bool is_device_ptr(const void* p) {
     return at.type == hipMemoryTypeDevice;
 }
 
+int64_t ipow_h(int64_t b, int e) {
+    int64_t v = 1;
+    while (e-- > 0) v *= b;
+    return v;
+}
+
 }  // namespace
+
+// Execution plan over a tree: which regions take part, how each folds
+// (observation space for few observations, knot space otherwise), storage
+// offsets, per-level task lists (host and device) and the algorithmic flop
+// counts of every launch.
+struct Plan {
+    std::vector<int8_t> form;
+    std::vector<int64_t> vst_off, gram_off;
+    int64_t vst_size = 1, gram_size = 1;
+    std::vector<std::vector<int>> prior_tasks, factor_tasks, gram_tasks;  // by level 1..M-1
+    std::vector<std::vector<int>> fsmall_tasks[3];  // factor folds with <= 16, 17..32, 33..64 rows
+    std::vector<int> leaf_tasks;                    // leaves with > 64 observations
+    std::vector<int> small_tasks[3];                // leaves with <= 16, 17..32, 33..64 observations
+    std::vector<int> chain_obs_tasks;               // level-(M-1) regions with observations
+    int64_t scratch_leaf = 0, scratch_fold = 0;     // doubles per workgroup slot
+    int root_gram = 0;
+    int64_t n_gram = 0;
+    // device copies
+    int8_t* d_form = nullptr;
+    int64_t *d_vst_off = nullptr, *d_gram_off = nullptr;
+    std::vector<int*> d_prior, d_factor, d_gramt, d_fsmall[3];
+    int *d_leaf = nullptr, *d_small[3] = {nullptr, nullptr, nullptr}, *d_chain_obs = nullptr;
+    // algorithmic FP64 flops of one theta
+    std::vector<double> fl_chain, fl_pfin, fl_factor, fl_gram, fl_fsmall[3];
+    double fl_chain_obs = 0.0, fl_leaf = 0.0, fl_small[3] = {0.0, 0.0, 0.0};
+
+    ~Plan() {
+        void* ps[] = {d_form, d_vst_off, d_gram_off, d_leaf, d_small[0], d_small[1], d_small[2], d_chain_obs};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+        for (auto* v : {&d_prior, &d_factor, &d_gramt, &d_fsmall[0], &d_fsmall[1], &d_fsmall[2]})
+            for (int* p : *v)
+                if (p) (void)hipFree(p);
+    }
+};
 
 struct mra_tree {
     HostTree h;
     int device = 0;
     uint32_t flags = 0;
-    // device copies
     double *d_x = nullptr, *d_y = nullptr, *d_z = nullptr, *d_box = nullptr;
-    int64_t *d_obs_lo = nullptr, *d_obs_hi = nullptr, *d_vst_off = nullptr, *d_gram_off = nullptr;
-    int8_t* d_form = nullptr;
-    // plan
-    std::vector<int8_t> form;
-    std::vector<int64_t> vst_off, gram_off;
-    int64_t vst_size = 0, gram_size = 0;
-    int WF = 1, WFs = 2;
-    std::vector<std::vector<int>> prior_tasks, factor_tasks, gram_tasks;  // index by level (1..M-1)
-    std::vector<int> leaf_tasks;                     // leaves with > 64 observations
-    std::vector<int> small_tasks[3];                 // leaves with <= 16, 17..32, 33..64 observations
-    std::vector<std::vector<int>> fsmall_tasks[3];   // factor folds with <= 16, 17..32, 33..64 rows, by level
-    std::vector<int*> d_prior, d_factor, d_gramt, d_fsmall[3];
-    int* d_leaf = nullptr;
-    int* d_small[3] = {nullptr, nullptr, nullptr};
-    int64_t scratch_leaf = 0, scratch_fold = 0;  // doubles per workgroup slot
-    int root_gram = 0;
-    int64_t n_gram = 0, leaf_min = 0, leaf_max = 0;
-    // algorithmic FP64 flops of one theta, per launch kind and level
-    std::vector<double> fl_chain, fl_pfin, fl_factor, fl_gram;
-    double fl_leaf = 0.0, fl_small[3] = {0.0, 0.0, 0.0};
-    std::vector<double> fl_fsmall[3];
+    int64_t *d_obs_lo = nullptr, *d_obs_hi = nullptr;
+    int WF = 1, WFs = 4;
+    Plan lik;  // plan of the likelihood
+    int64_t leaf_min = 0, leaf_max = 0;
     void* ws = nullptr;  // Workspace*, owned
-
     ~mra_tree();
-    void free_device() {
-        void* ps[] = {d_x, d_y, d_z, d_box, d_obs_lo, d_obs_hi, d_vst_off, d_gram_off, d_form, d_leaf,
-                      d_small[0], d_small[1], d_small[2]};
-        for (void* p : ps) if (p) (void)hipFree(p);
-        for (auto* v : {&d_prior, &d_factor, &d_gramt, &d_fsmall[0], &d_fsmall[1], &d_fsmall[2]})
-            for (int* p : *v) if (p) (void)hipFree(p);
-    }
 };
 
 // Algorithmic FP64 flop counts of what each launch computes for one theta,
@@ -126,11 +142,10 @@ struct mra_tree {
 //   factor fold, m       : n^2 p + n^3/3 + n^2 ((m-1) p + 1)
 //   Gram fold, m         : sum_children n_c D^2 + p^3/3 + (D-p) p^2 + (D-p)^2 p,
 //                          D = m p + 1 (Gram-form children: D^2/2 additions)
-static void plan_flops(mra_tree& t) {
-    const HostTree& h = t.h;
+static void plan_flops(const HostTree& h, Plan& t) {
     const int M = h.M;
     const double p = h.rhat;
-    t.fl_chain.assign(M + 1, 0.0);
+    t.fl_chain.assign(M, 0.0);
     t.fl_pfin.assign(M, 0.0);
     t.fl_factor.assign(M, 0.0);
     t.fl_gram.assign(M, 0.0);
@@ -160,15 +175,103 @@ static void plan_flops(mra_tree& t) {
         }
     }
     const double L = M - 1;
-    t.fl_chain[M] = double(h.n_used) * p * p * L * L;
+    t.fl_chain_obs = double(h.n_used) * p * p * L * L;
     auto fl = [&](int g) {
         const double n = double(h.obs_hi[g] - h.obs_lo[g]);
         return L * n * n * p + n * n * n / 3.0 + n * n * (L * p + 1);
     };
-    t.fl_leaf = t.fl_small[0] = t.fl_small[1] = t.fl_small[2] = 0.0;
+    t.fl_leaf = 0.0;
     for (int g : t.leaf_tasks) t.fl_leaf += fl(g);
-    for (int q = 0; q < 3; ++q)
+    for (int q = 0; q < 3; ++q) {
+        t.fl_small[q] = 0.0;
         for (int g : t.small_tasks[q]) t.fl_small[q] += fl(g);
+    }
+}
+
+// Build a plan.  active[g] (optional) marks regions whose prior is needed
+// beyond those holding observations (prediction points); gram_only forces
+// every fold into knot space.
+static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const std::vector<int64_t>* extra_count,
+                     Plan& t, std::string& err) {
+    const int M = h.M, P = h.P;
+    t.form.assign(h.nreg, FOLD_FACTOR);
+    t.vst_off.assign(h.nreg, -1);
+    t.gram_off.assign(h.nreg, -1);
+    t.prior_tasks.assign(M, {});
+    t.factor_tasks.assign(M, {});
+    t.gram_tasks.assign(M, {});
+    for (int q = 0; q < 3; ++q) t.fsmall_tasks[q].assign(M, {});
+    int64_t vo = 0, go = 0;
+    for (int m = 1; m < M; ++m) {
+        const int64_t thr = (gram_only || (flags & MRA_FOLD_GRAM)) ? 0
+                            : (flags & MRA_FOLD_FACTOR) ? 4096
+                            : std::min<int64_t>(int64_t(m - 1) * P + 1, factor_fold_max());
+        const int64_t D = int64_t(m) * P + 1;
+        for (int64_t g = h.lvl_start[m - 1]; g < h.lvl_start[m]; ++g) {
+            const int64_t np = h.obs_hi[g] - h.obs_lo[g];
+            const int64_t ne = extra_count ? (*extra_count)[g] : 0;
+            if (np == 0 && ne == 0) continue;  // nothing below: no prior, no fold
+            t.prior_tasks[m].push_back(int(g));
+            t.vst_off[g] = vo;
+            vo += int64_t(m) * P * P;
+            if (np == 0) continue;             // prior only (prediction points below)
+            if (np <= thr) {
+                t.form[g] = FOLD_FACTOR;
+                if (np <= 16) t.fsmall_tasks[0][m].push_back(int(g));
+                else if (np <= 32) t.fsmall_tasks[1][m].push_back(int(g));
+                else if (np <= 64) t.fsmall_tasks[2][m].push_back(int(g));
+                else t.factor_tasks[m].push_back(int(g));
+                if (np > 64) t.scratch_fold = std::max(t.scratch_fold, np * np);
+            } else {
+                t.form[g] = FOLD_GRAM;
+                t.gram_tasks[m].push_back(int(g));
+                t.gram_off[g] = go;
+                go += D * D;
+                ++t.n_gram;
+            }
+        }
+        if (m == M - 1)
+            for (int g : t.prior_tasks[m])
+                if (h.obs_hi[g] > h.obs_lo[g]) t.chain_obs_tasks.push_back(g);
+    }
+    t.vst_size = std::max<int64_t>(vo, 1);
+    t.gram_size = std::max<int64_t>(go, 1);
+    for (int64_t g = h.lvl_start[M - 1]; g < h.lvl_start[M]; ++g) {
+        const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
+        if (nc > 64) {
+            t.leaf_tasks.push_back(int(g));
+            t.scratch_leaf = std::max(t.scratch_leaf, nc * nc);
+        } else if (nc > 32) {
+            t.small_tasks[2].push_back(int(g));
+        } else if (nc > 16) {
+            t.small_tasks[1].push_back(int(g));
+        } else if (nc > 0) {
+            t.small_tasks[0].push_back(int(g));
+        }
+    }
+    t.root_gram = (M > 1 && t.form[0] == FOLD_GRAM && t.gram_off[0] >= 0) ? 1 : 0;
+    plan_flops(h, t);
+    int rc;
+    if ((rc = upload(&t.d_vst_off, t.vst_off)) || (rc = upload(&t.d_gram_off, t.gram_off)) ||
+        (rc = upload(&t.d_form, t.form)) || (rc = upload(&t.d_leaf, t.leaf_tasks)) ||
+        (rc = upload(&t.d_small[0], t.small_tasks[0])) || (rc = upload(&t.d_small[1], t.small_tasks[1])) ||
+        (rc = upload(&t.d_small[2], t.small_tasks[2])) || (rc = upload(&t.d_chain_obs, t.chain_obs_tasks))) {
+        err = "device allocation failed for the execution plan";
+        return rc;
+    }
+    t.d_prior.assign(M, nullptr);
+    t.d_factor.assign(M, nullptr);
+    t.d_gramt.assign(M, nullptr);
+    for (int q = 0; q < 3; ++q) t.d_fsmall[q].assign(M, nullptr);
+    for (int m = 1; m < M; ++m)
+        if ((rc = upload(&t.d_prior[m], t.prior_tasks[m])) || (rc = upload(&t.d_factor[m], t.factor_tasks[m])) ||
+            (rc = upload(&t.d_gramt[m], t.gram_tasks[m])) || (rc = upload(&t.d_fsmall[0][m], t.fsmall_tasks[0][m])) ||
+            (rc = upload(&t.d_fsmall[1][m], t.fsmall_tasks[1][m])) ||
+            (rc = upload(&t.d_fsmall[2][m], t.fsmall_tasks[2][m]))) {
+            err = "device allocation failed for the execution plan";
+            return rc;
+        }
+    return MRA_OK;
 }
 
 // ---- optional per-launch timing (HIP events around every launch) ----------
@@ -195,7 +298,7 @@ hipEvent_t pooled_event() {
     return e;
 }
 const char* const KIND_NAMES[] = {"k_chain", "k_prior_finish", "k_leaf_finish", "k_fold_factor", "k_fold_gram",
-                                  "k_final", "k_small_leaf", "k_small_fold"};
+                                  "k_final", "k_small_leaf", "k_small_fold", "k_pred_leaf", "k_pred_fold"};
 }  // namespace
 
 template <class F>
@@ -312,96 +415,30 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
     rc = build_host_tree(px, py, pz, n, J, r, M, offset, domain4, t->h, err);
     if (rc) { delete t; return fail(rc, err); }
     const HostTree& h = t->h;
-    const int P = h.P;
-    if (M - 1 > chain_lmax(P)) {
+    if (M - 1 > chain_lmax(h.P)) {
         delete t;
-        return fail(MRA_EINVAL, "M - 1 = " + std::to_string(M - 1) + " exceeds " + std::to_string(chain_lmax(P)) +
-                                    " levels above the finest for r_hat padded to " + std::to_string(P));
+        return fail(MRA_EINVAL, "M - 1 = " + std::to_string(M - 1) + " exceeds " + std::to_string(chain_lmax(h.P)) +
+                                    " levels above the finest");
     }
-
-    // plan: fold form of every non-leaf region, storage offsets, task lists
-    t->form.assign(h.nreg, FOLD_FACTOR);
-    t->vst_off.assign(h.nreg, -1);
-    t->gram_off.assign(h.nreg, -1);
-    t->prior_tasks.assign(M, {});
-    t->factor_tasks.assign(M, {});
-    t->gram_tasks.assign(M, {});
-    for (int q = 0; q < 3; ++q) t->fsmall_tasks[q].assign(M, {});
-    int64_t vo = 0, go = 0;
-    for (int m = 1; m < M; ++m) {
-        const int64_t thr = (flags & MRA_FOLD_GRAM) ? 0
-                            : (flags & MRA_FOLD_FACTOR) ? 4096
-                            : std::min<int64_t>(int64_t(m - 1) * P + 1, factor_fold_max());
-        const int64_t D = int64_t(m) * P + 1;
-        for (int64_t g = h.lvl_start[m - 1]; g < h.lvl_start[m]; ++g) {
-            const int64_t np = h.obs_hi[g] - h.obs_lo[g];
-            if (np == 0) continue;  // empty subtree: contributes nothing
-            t->prior_tasks[m].push_back(int(g));
-            t->vst_off[g] = vo;
-            vo += int64_t(m) * P * P;
-            if (np <= thr) {
-                t->form[g] = FOLD_FACTOR;
-                if (np <= 16) t->fsmall_tasks[0][m].push_back(int(g));
-                else if (np <= 32) t->fsmall_tasks[1][m].push_back(int(g));
-                else if (np <= 64) t->fsmall_tasks[2][m].push_back(int(g));
-                else t->factor_tasks[m].push_back(int(g));
-                if (np > 64) t->scratch_fold = std::max(t->scratch_fold, np * np);
-            } else {
-                t->form[g] = FOLD_GRAM;
-                t->gram_tasks[m].push_back(int(g));
-                t->gram_off[g] = go;
-                go += D * D;
-                ++t->n_gram;
-            }
-        }
-    }
-    t->vst_size = std::max<int64_t>(vo, 1);
-    t->gram_size = std::max<int64_t>(go, 1);
+    t->WF = (M - 1) * h.P + 1;
+    t->WFs = (t->WF + 3) & ~3;
     t->leaf_min = INT64_MAX;
     for (int64_t g = h.lvl_start[M - 1]; g < h.lvl_start[M]; ++g) {
         const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
         t->leaf_min = std::min(t->leaf_min, nc);
         t->leaf_max = std::max(t->leaf_max, nc);
-        if (nc > 64) {
-            t->leaf_tasks.push_back(int(g));
-            t->scratch_leaf = std::max(t->scratch_leaf, nc * nc);
-        } else if (nc > 32) {
-            t->small_tasks[2].push_back(int(g));
-        } else if (nc > 16) {
-            t->small_tasks[1].push_back(int(g));
-        } else if (nc > 0) {
-            t->small_tasks[0].push_back(int(g));
-        }
     }
     if (t->leaf_min == INT64_MAX) t->leaf_min = 0;
-    t->WF = (M - 1) * P + 1;
-    t->WFs = (t->WF + 3) & ~3;
-    t->root_gram = (M > 1 && t->form[0] == FOLD_GRAM) ? 1 : 0;
-    plan_flops(*t);
-
-    // device copies
+    if ((rc = make_plan(h, flags, false, nullptr, t->lik, err))) {
+        delete t;
+        return fail(rc, err);
+    }
     std::vector<int64_t> lo(h.obs_lo), hi(h.obs_hi);
     if ((rc = upload(&t->d_x, h.x)) || (rc = upload(&t->d_y, h.y)) || (rc = upload(&t->d_z, h.z)) ||
-        (rc = upload(&t->d_box, h.box)) || (rc = upload(&t->d_obs_lo, lo)) || (rc = upload(&t->d_obs_hi, hi)) ||
-        (rc = upload(&t->d_vst_off, t->vst_off)) || (rc = upload(&t->d_gram_off, t->gram_off)) ||
-        (rc = upload(&t->d_form, t->form)) || (rc = upload(&t->d_leaf, t->leaf_tasks)) ||
-        (rc = upload(&t->d_small[0], t->small_tasks[0])) || (rc = upload(&t->d_small[1], t->small_tasks[1])) ||
-        (rc = upload(&t->d_small[2], t->small_tasks[2]))) {
+        (rc = upload(&t->d_box, h.box)) || (rc = upload(&t->d_obs_lo, lo)) || (rc = upload(&t->d_obs_hi, hi))) {
         delete t;
         return fail(rc, "device allocation or copy failed while uploading the tree");
     }
-    t->d_prior.assign(M, nullptr);
-    t->d_factor.assign(M, nullptr);
-    t->d_gramt.assign(M, nullptr);
-    for (int q = 0; q < 3; ++q) t->d_fsmall[q].assign(M, nullptr);
-    for (int m = 1; m < M; ++m)
-        if ((rc = upload(&t->d_prior[m], t->prior_tasks[m])) || (rc = upload(&t->d_factor[m], t->factor_tasks[m])) ||
-            (rc = upload(&t->d_gramt[m], t->gram_tasks[m])) || (rc = upload(&t->d_fsmall[0][m], t->fsmall_tasks[0][m])) ||
-            (rc = upload(&t->d_fsmall[1][m], t->fsmall_tasks[1][m])) ||
-            (rc = upload(&t->d_fsmall[2][m], t->fsmall_tasks[2][m]))) {
-            delete t;
-            return fail(rc, "device allocation failed for task lists");
-        }
     *out = t;
     return MRA_OK;
 }
@@ -413,7 +450,7 @@ extern "C" int mra_tree_info(const mra_tree* t, mra_info* info) {
     info->J = h.J; info->M = h.M; info->r = h.r; info->r_hat = h.rhat; info->P = h.P;
     info->n_regions = h.nreg; info->n_leaves = h.nleaf;
     info->leaf_min = t->leaf_min; info->leaf_max = t->leaf_max;
-    info->n_gram_regions = t->n_gram;
+    info->n_gram_regions = t->lik.n_gram;
     return MRA_OK;
 }
 
@@ -446,10 +483,109 @@ static int region_level(const HostTree& h, int64_t g) {
     return h.M;
 }
 
-#define HIPCHK(expr)                                                                        \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess) { rc = fail(MRA_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); goto done; } \
+static bool theta_ok(const double* q) {
+    return q[0] > 0.0 && q[1] > 0.0 && q[2] > 0.0 && std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]);
+}
+
+// Kernel arguments common to every launch over a tree and plan.
+static KArgs base_args(const mra_tree* t, const Plan& pl, int smooth) {
+    const HostTree& h = t->h;
+    KArgs a{};
+    a.x = t->d_x; a.y = t->d_y; a.z = t->d_z; a.box = t->d_box;
+    a.obs_lo = t->d_obs_lo; a.obs_hi = t->d_obs_hi;
+    a.vst_off = pl.d_vst_off; a.gram_off = pl.d_gram_off; a.form = pl.d_form;
+    for (int m = 0; m <= h.M && m <= MAXL; ++m) a.lvl[m] = h.lvl_start[m];
+    a.J = h.J; a.M = h.M; a.nx = h.nx; a.ny = h.ny; a.rhat = h.rhat; a.P = h.P; a.WF = t->WF; a.WFs = t->WFs;
+    a.offset = h.offset; a.smooth = smooth;
+    a.vst_stride = pl.vst_size;
+    a.F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
+    a.gram_stride = pl.gram_size;
+    a.d_stride = h.nreg;
+    a.n_used = double(h.n_used);
+    return a;
+}
+
+// Prior (levels 1..M-1) and the observations' whitened rows for one chunk.
+static hipError_t enqueue_prior(const mra_tree* t, const Plan& pl, KArgs a, int nb, hipStream_t st) {
+    const int M = t->h.M;
+    hipError_t e;
+    for (int m = 1; m < M; ++m) {
+        a.level = m;
+        a.tasks = pl.d_prior[m];
+        a.ntasks = int64_t(pl.prior_tasks[m].size());
+        if (a.ntasks == 0) continue;
+        const int grid = int(std::min<int64_t>(a.ntasks * nb, 1 << 16));
+        if (m > 1 && (e = timed(0, m, pl.fl_chain[m] * nb, st, [&] { return launch_chain(a, 0, grid, st); }))) return e;
+        if ((e = timed(1, m, pl.fl_pfin[m] * nb, st, [&] { return launch_prior_finish(a, grid, st); }))) return e;
+    }
+    if (M > 1 && !pl.chain_obs_tasks.empty()) {
+        a.level = M - 1;
+        a.tasks = pl.d_chain_obs;
+        a.ntasks = int64_t(pl.chain_obs_tasks.size());
+        const int grid = int(std::min<int64_t>(a.ntasks * nb, 1 << 16));
+        if ((e = timed(0, M, pl.fl_chain_obs * nb, st, [&] { return launch_chain(a, 1, grid, st); }))) return e;
+    }
+    return hipSuccess;
+}
+
+// Finest-level factors of the observations for one chunk.
+static hipError_t enqueue_leaves(const mra_tree* t, const Plan& pl, KArgs a, int nb, int64_t nslot, hipStream_t st) {
+    const int M = t->h.M;
+    hipError_t e;
+    a.level = M;
+    for (int q = 0; q < 3; ++q) {
+        a.tasks = pl.d_small[q];
+        a.ntasks = int64_t(pl.small_tasks[q].size());
+        if (a.ntasks > 0 && (e = timed(6, M, pl.fl_small[q] * nb, st, [&] {
+                                 return launch_small(a, 16 << q, 0, int(std::min<int64_t>(a.ntasks * nb, 1 << 18)), st);
+                             })))
+            return e;
+    }
+    a.tasks = pl.d_leaf;
+    a.ntasks = int64_t(pl.leaf_tasks.size());
+    if (a.ntasks > 0 && (e = timed(2, M, pl.fl_leaf * nb, st, [&] {
+                             return launch_leaf(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st);
+                         })))
+        return e;
+    return hipSuccess;
+}
+
+// Fold of level m for one chunk.
+static hipError_t enqueue_fold(const mra_tree* t, const Plan& pl, KArgs a, int m, int nb, int64_t nslot,
+                               hipStream_t st) {
+    (void)t;
+    hipError_t e;
+    a.level = m;
+    for (int q = 0; q < 3; ++q) {
+        a.tasks = pl.d_fsmall[q][m];
+        a.ntasks = int64_t(pl.fsmall_tasks[q][m].size());
+        if (a.ntasks > 0 && (e = timed(7, m, pl.fl_fsmall[q][m] * nb, st, [&] {
+                                 return launch_small(a, 16 << q, 1, int(std::min<int64_t>(a.ntasks * nb, 1 << 18)), st);
+                             })))
+            return e;
+    }
+    a.tasks = pl.d_factor[m];
+    a.ntasks = int64_t(pl.factor_tasks[m].size());
+    if (a.ntasks > 0 && (e = timed(3, m, pl.fl_factor[m] * nb, st, [&] {
+                             return launch_fold_factor(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st);
+                         })))
+        return e;
+    a.tasks = pl.d_gramt[m];
+    a.ntasks = int64_t(pl.gram_tasks[m].size());
+    if (a.ntasks > 0 && (e = timed(4, m, pl.fl_gram[m] * nb, st, [&] {
+                             return launch_fold_gram(a, int(std::min<int64_t>(a.ntasks * nb, 1 << 16)), st);
+                         })))
+        return e;
+    return hipSuccess;
+}
+
+#define HIPCHK(expr)                                                                                      \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
+        if (e_ != hipSuccess) {                                                                           \
+            rc = fail(MRA_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_));                      \
+            goto done;                                                                                    \
+        }                                                                                                 \
     } while (0)
 
 // Device workspace of a tree, kept between calls (allocation of the large
@@ -464,8 +600,15 @@ struct Workspace {
     hipEvent_t done = nullptr;
     hipStream_t last = nullptr;
     bool used = false;
+    // captured graphs of whole evaluations, keyed by (theta, out, B, smooth, stream)
+    std::map<std::tuple<const void*, void*, int64_t, int, void*>, hipGraphExec_t> graphs;
+    void drop_graphs() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
     void release() {
         if (done) { (void)hipEventSynchronize(done); (void)hipEventDestroy(done); done = nullptr; }
+        drop_graphs();
         for (void* p : {static_cast<void*>(vst), static_cast<void*>(F), static_cast<void*>(gram),
                         static_cast<void*>(dval), static_cast<void*>(scratch), static_cast<void*>(th),
                         static_cast<void*>(out), static_cast<void*>(status)})
@@ -479,19 +622,32 @@ struct Workspace {
 
 static std::mutex g_ws_mu;
 
-static Workspace& workspace_of(const mra_tree* t);
+static Workspace& workspace_of(const mra_tree* t) {
+    auto* mt = const_cast<mra_tree*>(t);
+    if (!mt->ws) mt->ws = new Workspace();
+    return *static_cast<Workspace*>(mt->ws);
+}
+
+mra_tree::~mra_tree() {
+    if (ws) {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        static_cast<Workspace*>(ws)->release();
+        delete static_cast<Workspace*>(ws);
+    }
+    void* ps[] = {d_x, d_y, d_z, d_box, d_obs_lo, d_obs_hi};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+}
 
 static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStream_t st) {
     const HostTree& h = t->h;
+    const Plan& pl = t->lik;
     const int64_t F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
-    const int64_t per_theta = t->vst_size + F_stride + t->gram_size + h.nreg;
-    const int64_t scratch_per = std::max<int64_t>({t->scratch_leaf, t->scratch_fold, 1});
+    const int64_t per_theta = pl.vst_size + F_stride + pl.gram_size + h.nreg;
+    const int64_t scratch_per = std::max<int64_t>({pl.scratch_leaf, pl.scratch_fold, 1});
     // reuse when the buffers hold enough theta per chunk (or could not hold more)
     if (w.Bc > 0 && w.cap_B >= B && (w.Bc >= B || w.mem_limited)) return MRA_OK;
-    if (w.Bc > 0) {
-        // grow: wait for the last user, release, reallocate
-        w.release();
-    }
+    if (w.Bc > 0) w.release();
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(MRA_EDEVICE, "hipMemGetInfo failed");
     const double budget = 0.6 * double(free_b) / 8.0;  // doubles
@@ -501,9 +657,9 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
     if (Bc < 1) return fail(MRA_ENOMEM, "not enough device memory for one theta");
     const int64_t capB = std::max<int64_t>(B, 64);
     auto al = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 8)) == hipSuccess; };
-    if (!al(reinterpret_cast<void**>(&w.vst), size_t(Bc) * t->vst_size * 8) ||
+    if (!al(reinterpret_cast<void**>(&w.vst), size_t(Bc) * pl.vst_size * 8) ||
         !al(reinterpret_cast<void**>(&w.F), size_t(Bc) * F_stride * 8) ||
-        !al(reinterpret_cast<void**>(&w.gram), size_t(Bc) * t->gram_size * 8) ||
+        !al(reinterpret_cast<void**>(&w.gram), size_t(Bc) * pl.gram_size * 8) ||
         !al(reinterpret_cast<void**>(&w.dval), size_t(Bc) * h.nreg * 8) ||
         !al(reinterpret_cast<void**>(&w.scratch), size_t(nslot) * scratch_per * 8) ||
         !al(reinterpret_cast<void**>(&w.status), size_t(capB) * sizeof(int)) ||
@@ -526,6 +682,36 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
     return MRA_OK;
 }
 
+// Every launch of one evaluation of B parameter vectors (chunks of Bc).
+static hipError_t enqueue_loglik(const mra_tree* t, Workspace& w, KArgs a, const double* d_th, double* d_out,
+                                 int* status, int64_t B, hipStream_t st) {
+    const HostTree& h = t->h;
+    const Plan& pl = t->lik;
+    hipError_t e;
+    if ((e = launch_fill_int(status, B, 0, st))) return e;
+    for (int64_t b0 = 0; b0 < B; b0 += w.Bc) {
+        const int nb = int(std::min<int64_t>(w.Bc, B - b0));
+        a.theta = d_th + 3 * b0;
+        a.ntheta = nb;
+        a.status = status + b0;
+        a.out = d_out + b0;
+        if ((e = launch_fill(w.dval, int64_t(nb) * h.nreg, 0.0, st))) return e;
+        if ((e = enqueue_prior(t, pl, a, nb, st))) return e;
+        if ((e = enqueue_leaves(t, pl, a, nb, w.nslot, st))) return e;
+        for (int m = h.M - 1; m >= 1; --m)
+            if ((e = enqueue_fold(t, pl, a, m, nb, w.nslot, st))) return e;
+        if ((e = timed(5, 0, 0.0, st, [&] { return launch_final(a, h.nreg, pl.root_gram, st); }))) return e;
+    }
+    return hipSuccess;
+}
+
+// Repeated evaluations with device pointers on a non-null stream replay a
+// captured graph of the whole launch sequence (MRA_GRAPHS=0 disables this).
+static bool graphs_enabled() {
+    const char* e = std::getenv("MRA_GRAPHS");
+    return !(e && *e == '0');
+}
+
 extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double* theta, int64_t B,
                           double* loglik, void* stream) {
     if (!t || !theta || !loglik || B < 1) return fail(MRA_EINVAL, "NULL argument or B < 1");
@@ -536,100 +722,49 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const bool dev = is_device_ptr(theta);
     if (dev != is_device_ptr(loglik)) return fail(MRA_EINVAL, "theta and loglik must be in the same memory space");
-    if (!dev) {
-        for (int64_t b = 0; b < B; ++b) {
-            const double* q = theta + 3 * b;
-            if (!(q[0] > 0.0) || !(q[1] > 0.0) || !(q[2] > 0.0) || !std::isfinite(q[0]) || !std::isfinite(q[1]) ||
-                !std::isfinite(q[2]))
+    if (!dev)
+        for (int64_t b = 0; b < B; ++b)
+            if (!theta_ok(theta + 3 * b))
                 return fail(MRA_EINVAL, "theta " + std::to_string(b) + ": alpha, beta, tau must be finite and > 0");
-        }
-    }
-    const int M = h.M, P = h.P;
-    const int64_t F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
 
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace& w = workspace_of(t);
     rc = ensure_workspace(t, w, B, st);
     if (rc) return rc;
     if (w.used && w.last != st) (void)hipStreamWaitEvent(st, w.done, 0);
-    const int64_t Bc = w.Bc, nslot = w.nslot;
     double* d_th = dev ? const_cast<double*>(theta) : w.th;
     double* d_out = dev ? loglik : w.out;
-    int* status = w.status;
     std::vector<int> hstatus;
-    KArgs a{};
-    if (!dev) HIPCHK(hipMemcpyAsync(d_th, theta, 3 * B * 8, hipMemcpyHostToDevice, st));
-    HIPCHK(launch_fill_int(status, B, 0, st));
-
-    a.x = t->d_x; a.y = t->d_y; a.z = t->d_z; a.box = t->d_box;
-    a.obs_lo = t->d_obs_lo; a.obs_hi = t->d_obs_hi;
-    a.vst_off = t->d_vst_off; a.gram_off = t->d_gram_off; a.form = t->d_form;
-    for (int m = 0; m <= M && m <= MAXL; ++m) a.lvl[m] = h.lvl_start[m];
-    a.J = h.J; a.M = M; a.nx = h.nx; a.ny = h.ny; a.rhat = h.rhat; a.P = P; a.WF = t->WF; a.WFs = t->WFs;
-    a.offset = h.offset; a.smooth = smooth;
-    a.vst = w.vst; a.vst_stride = t->vst_size;
-    a.F = w.F; a.F_stride = F_stride;
-    a.gram = w.gram; a.gram_stride = t->gram_size;
-    a.dval = w.dval; a.d_stride = h.nreg;
+    KArgs a = base_args(t, t->lik, smooth);
+    a.vst = w.vst; a.F = w.F; a.gram = w.gram; a.dval = w.dval;
     a.scratch = w.scratch; a.scratch_stride = w.scratch_per;
-    a.n_used = double(h.n_used);
-
-    for (int64_t b0 = 0; b0 < B; b0 += Bc) {
-        const int nb = int(std::min<int64_t>(Bc, B - b0));
-        a.theta = d_th + 3 * b0;
-        a.ntheta = nb;
-        a.status = status + b0;
-        a.out = d_out + b0;
-        HIPCHK(launch_fill(w.dval, int64_t(nb) * h.nreg, 0.0, st));
-        for (int m = 1; m < M; ++m) {
-            a.level = m;
-            a.tasks = t->d_prior[m];
-            a.ntasks = int64_t(t->prior_tasks[m].size());
-            if (a.ntasks == 0) continue;
-            const int grid = int(std::min<int64_t>(a.ntasks * nb, 1 << 16));
-            if (m > 1) HIPCHK(timed(0, m, t->fl_chain[m] * nb, st, [&] { return launch_chain(a, 0, grid, st); }));
-            HIPCHK(timed(1, m, t->fl_pfin[m] * nb, st, [&] { return launch_prior_finish(a, grid, st); }));
+    bool profiling;
+    {
+        std::lock_guard<std::mutex> pk(g_prof_mu);
+        profiling = g_prof_on;
+    }
+    if (!dev) HIPCHK(hipMemcpyAsync(d_th, theta, 3 * B * 8, hipMemcpyHostToDevice, st));
+    if (dev && st != nullptr && !profiling && graphs_enabled()) {
+        // a repeated evaluation on the same buffers replays one captured graph
+        const auto key = std::make_tuple(static_cast<const void*>(theta), static_cast<void*>(loglik), B, smooth,
+                                         static_cast<void*>(st));
+        auto it = w.graphs.find(key);
+        if (it == w.graphs.end()) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            const hipError_t ce = enqueue_loglik(t, w, a, d_th, d_out, w.status, B, st);
+            const hipError_t ee = hipStreamEndCapture(st, &g);
+            HIPCHK(ce);
+            HIPCHK(ee);
+            const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIPCHK(ie);
+            it = w.graphs.emplace(key, ge).first;
         }
-        if (M > 1 && !t->prior_tasks[M - 1].empty()) {
-            a.level = M - 1;
-            a.tasks = t->d_prior[M - 1];
-            a.ntasks = int64_t(t->prior_tasks[M - 1].size());
-            const int grid = int(std::min<int64_t>(a.ntasks * nb, 1 << 16));
-            HIPCHK(timed(0, M, t->fl_chain[M] * nb, st, [&] { return launch_chain(a, 1, grid, st); }));
-        }
-        a.level = M;
-        for (int q = 0; q < 3; ++q) {
-            a.tasks = t->d_small[q];
-            a.ntasks = int64_t(t->small_tasks[q].size());
-            if (a.ntasks > 0)
-                HIPCHK(timed(6, M, t->fl_small[q] * nb, st, [&] {
-                    return launch_small(a, 16 << q, 0, int(std::min<int64_t>(a.ntasks * nb, 1 << 18)), st);
-                }));
-        }
-        a.tasks = t->d_leaf;
-        a.ntasks = int64_t(t->leaf_tasks.size());
-        if (a.ntasks > 0)
-            HIPCHK(timed(2, M, t->fl_leaf * nb, st, [&] { return launch_leaf(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st); }));
-        for (int m = M - 1; m >= 1; --m) {
-            a.level = m;
-            for (int q = 0; q < 3; ++q) {
-                a.tasks = t->d_fsmall[q][m];
-                a.ntasks = int64_t(t->fsmall_tasks[q][m].size());
-                if (a.ntasks > 0)
-                    HIPCHK(timed(7, m, t->fl_fsmall[q][m] * nb, st, [&] {
-                        return launch_small(a, 16 << q, 1, int(std::min<int64_t>(a.ntasks * nb, 1 << 18)), st);
-                    }));
-            }
-            a.tasks = t->d_factor[m];
-            a.ntasks = int64_t(t->factor_tasks[m].size());
-            if (a.ntasks > 0)
-                HIPCHK(timed(3, m, t->fl_factor[m] * nb, st, [&] { return launch_fold_factor(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st); }));
-            a.tasks = t->d_gramt[m];
-            a.ntasks = int64_t(t->gram_tasks[m].size());
-            if (a.ntasks > 0)
-                HIPCHK(timed(4, m, t->fl_gram[m] * nb, st, [&] { return launch_fold_gram(a, int(std::min<int64_t>(a.ntasks * nb, 1 << 16)), st); }));
-        }
-        HIPCHK(timed(5, 0, 0.0, st, [&] { return launch_final(a, h.nreg, t->root_gram, st); }));
+        HIPCHK(hipGraphLaunch(it->second, st));
+    } else {
+        HIPCHK(enqueue_loglik(t, w, a, d_th, d_out, w.status, B, st));
     }
     (void)hipEventRecord(w.done, st);
     w.last = st;
@@ -637,7 +772,7 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
     if (!dev) {
         HIPCHK(hipMemcpyAsync(loglik, d_out, B * 8, hipMemcpyDeviceToHost, st));
         hstatus.resize(B);
-        HIPCHK(hipMemcpyAsync(hstatus.data(), status, B * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hstatus.data(), w.status, B * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         for (int64_t b = 0; b < B; ++b)
             if (hstatus[b] != 0) {
@@ -652,24 +787,153 @@ done:
     return rc;
 }
 
-static Workspace& workspace_of(const mra_tree* t) {
-    auto* mt = const_cast<mra_tree*>(t);
-    if (!mt->ws) mt->ws = new Workspace();
-    return *static_cast<Workspace*>(mt->ws);
-}
-
-mra_tree::~mra_tree() {
-    if (ws) {
-        std::lock_guard<std::mutex> lk(g_ws_mu);
-        static_cast<Workspace*>(ws)->release();
-        delete static_cast<Workspace*>(ws);
-    }
-    free_device();
-}
+// ---------------------------------------------------------------- kriging
 
 extern "C" int mra_predict(const mra_tree* t, int family, double nu, const double* theta, const double* px,
                            const double* py, int64_t np, double* mean, double* var, void* stream) {
-    (void)t; (void)family; (void)nu; (void)theta; (void)px; (void)py; (void)np; (void)mean; (void)var;
-    (void)stream;
-    return fail(MRA_EINVAL, "mra_predict is not available in this build yet");
+    if (!t || !theta || (np > 0 && (!px || !py || !mean || !var)) || np < 0)
+        return fail(MRA_EINVAL, "NULL argument or np < 0");
+    int smooth = 0;
+    int rc = smooth_of(family, nu, &smooth);
+    if (rc) return rc;
+    if (np == 0) return MRA_OK;
+    const HostTree& h = t->h;
+    const int M = h.M;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const bool dev = is_device_ptr(px);
+    if (dev != is_device_ptr(py) || dev != is_device_ptr(mean) || dev != is_device_ptr(var) ||
+        dev != is_device_ptr(theta))
+        return fail(MRA_EINVAL, "theta, px, py, mean and var must all be host or all device pointers");
+    double th[3];
+    std::vector<double> hx(np), hy(np);
+    if (dev) {
+        if (hipMemcpy(th, theta, 24, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(hx.data(), px, np * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(hy.data(), py, np * 8, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(MRA_EDEVICE, "copy of device inputs failed");
+    } else {
+        std::memcpy(th, theta, 24);
+        std::memcpy(hx.data(), px, np * 8);
+        std::memcpy(hy.data(), py, np * 8);
+    }
+    if (!theta_ok(th)) return fail(MRA_EINVAL, "alpha, beta, tau must be finite and > 0");
+    for (int64_t i = 0; i < np; ++i)
+        if (!std::isfinite(hx[i]) || !std::isfinite(hy[i])) return fail(MRA_EINVAL, "non-finite prediction location");
+    std::string err;
+    std::vector<int64_t> leaf;
+    if ((rc = locate_leaves(h, hx.data(), hy.data(), np, leaf, err))) return fail(rc, err);
+    // group the points by leaf (stable), ranges per region, counts per region
+    const int64_t l0 = h.lvl_start[M - 1];
+    std::vector<int64_t> cnt(h.nleaf + 1, 0);
+    for (int64_t i = 0; i < np; ++i) ++cnt[leaf[i] - l0 + 1];
+    for (int64_t k = 0; k < h.nleaf; ++k) cnt[k + 1] += cnt[k];
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1), perm(np), sleaf(np);
+    std::vector<double> sx(np), sy(np);
+    for (int64_t i = 0; i < np; ++i) {
+        const int64_t d = fill[leaf[i] - l0]++;
+        sx[d] = hx[i]; sy[d] = hy[i]; perm[d] = i; sleaf[d] = leaf[i];
+    }
+    std::vector<int64_t> plo(h.nreg), phi(h.nreg), pcount(h.nreg);
+    for (int m = 0; m < M; ++m) {
+        const int64_t span = ipow_h(h.J, M - 1 - m);
+        for (int64_t k = 0; k < ipow_h(h.J, m); ++k) {
+            const int64_t g = h.lvl_start[m] + k;
+            plo[g] = cnt[k * span];
+            phi[g] = cnt[(k + 1) * span];
+            pcount[g] = phi[g] - plo[g];
+        }
+    }
+    Plan pl;
+    if ((rc = make_plan(h, t->flags, true, &pcount, pl, err))) return fail(rc, err);
+    std::vector<int> pred_leaf_tasks, pred_chain_tasks;
+    for (int64_t g = h.lvl_start[M - 1]; g < h.lvl_start[M]; ++g)
+        if (pcount[g] > 0) pred_leaf_tasks.push_back(int(g));
+    if (M > 1)
+        for (int64_t g = h.lvl_start[M - 2]; g < h.lvl_start[M - 1]; ++g)
+            if (pcount[g] > 0) pred_chain_tasks.push_back(int(g));
+    int64_t kmax = 0, nmax = 0;
+    for (int g : pred_leaf_tasks) {
+        kmax = std::max(kmax, pcount[g]);
+        nmax = std::max(nmax, h.obs_hi[g] - h.obs_lo[g]);
+    }
+    // device buffers (one theta)
+    const int64_t F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
+    const int64_t scratch_per = std::max<int64_t>({pl.scratch_leaf, pl.scratch_fold, nmax * nmax + nmax * (t->WFs + kmax), 1});
+    const int64_t nslot = 256;
+    double *d_th = nullptr, *vst = nullptr, *F = nullptr, *gram = nullptr, *dval = nullptr, *scratch = nullptr,
+           *PV = nullptr, *PS = nullptr, *PVAR = nullptr, *d_px = nullptr, *d_py = nullptr, *d_mean = nullptr,
+           *d_var = nullptr, *out1 = nullptr;
+    int* status = nullptr;
+    int64_t *d_plo = nullptr, *d_phi = nullptr, *d_sleaf = nullptr, *d_perm = nullptr;
+    int *d_pleaf = nullptr, *d_pchain = nullptr;
+    int hstatus = 0;
+    KArgs a = base_args(t, pl, smooth);
+    std::vector<double> thv(th, th + 3);
+    auto al = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 8)) == hipSuccess; };
+    if (!al(reinterpret_cast<void**>(&vst), pl.vst_size * 8) || !al(reinterpret_cast<void**>(&F), F_stride * 8) ||
+        !al(reinterpret_cast<void**>(&gram), pl.gram_size * 8) || !al(reinterpret_cast<void**>(&dval), h.nreg * 8) ||
+        !al(reinterpret_cast<void**>(&scratch), nslot * scratch_per * 8) ||
+        !al(reinterpret_cast<void**>(&PV), np * t->WFs * 8) || !al(reinterpret_cast<void**>(&PS), np * t->WFs * 8) ||
+        !al(reinterpret_cast<void**>(&PVAR), np * 8) || !al(reinterpret_cast<void**>(&status), sizeof(int)) ||
+        !al(reinterpret_cast<void**>(&out1), 8) || upload(&d_th, thv) || upload(&d_px, sx) || upload(&d_py, sy) ||
+        upload(&d_plo, plo) || upload(&d_phi, phi) || upload(&d_sleaf, sleaf) || upload(&d_perm, perm) ||
+        upload(&d_pleaf, pred_leaf_tasks) || upload(&d_pchain, pred_chain_tasks) ||
+        (!dev && (!al(reinterpret_cast<void**>(&d_mean), np * 8) || !al(reinterpret_cast<void**>(&d_var), np * 8)))) {
+        (void)hipGetLastError();
+        rc = fail(MRA_ENOMEM, "device allocation for prediction failed");
+        goto done;
+    }
+    a.vst = vst; a.F = F; a.gram = gram; a.dval = dval; a.scratch = scratch; a.scratch_stride = scratch_per;
+    a.theta = d_th; a.ntheta = 1; a.status = status; a.out = out1;
+    a.px = d_px; a.py = d_py; a.pred_lo = d_plo; a.pred_hi = d_phi; a.pred_leaf = d_sleaf; a.pred_perm = d_perm;
+    a.PV = PV; a.PS = PS; a.PVAR = PVAR; a.npred = np;
+    a.mean_out = dev ? mean : d_mean;
+    a.var_out = dev ? var : d_var;
+    HIPCHK(launch_fill_int(status, 1, 0, st));
+    HIPCHK(launch_fill(dval, h.nreg, 0.0, st));
+    HIPCHK(launch_fill(PV, np * t->WFs, 0.0, st));
+    HIPCHK(enqueue_prior(t, pl, a, 1, st));
+    if (M > 1 && !pred_chain_tasks.empty()) {
+        // the points' whitened rows: the observation chain over the points' arrays
+        KArgs b = a;
+        b.x = d_px; b.y = d_py; b.obs_lo = d_plo; b.obs_hi = d_phi;
+        b.F = PV; b.F_stride = np * t->WFs;
+        b.level = M - 1;
+        b.tasks = d_pchain;
+        b.ntasks = int64_t(pred_chain_tasks.size());
+        HIPCHK(launch_chain(b, 1, int(std::min<int64_t>(b.ntasks, 1 << 16)), st));
+    }
+    a.tasks = d_pleaf;
+    a.ntasks = int64_t(pred_leaf_tasks.size());
+    HIPCHK(timed(8, M, 0.0, st, [&] { return launch_pred_leaf(a, int(std::min<int64_t>(a.ntasks, nslot)), st); }));
+    HIPCHK(enqueue_leaves(t, pl, a, 1, nslot, st));
+    for (int m = M - 1; m >= 1; --m) {
+        HIPCHK(enqueue_fold(t, pl, a, m, 1, nslot, st));
+        a.level = m;
+        HIPCHK(timed(9, m, 0.0, st, [&] { return launch_pred_fold(a, st); }));
+    }
+    HIPCHK(launch_pred_out(a, st));
+    if (!dev) {
+        HIPCHK(hipMemcpyAsync(mean, d_mean, np * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(var, d_var, np * 8, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipMemcpyAsync(&hstatus, status, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hstatus != 0) {
+        const int64_t g = hstatus - 1;
+        const int lev = region_level(h, g);
+        rc = fail(MRA_ENOTPD, "not positive definite: level " + std::to_string(lev) + ", region " +
+                                  std::to_string(g - h.lvl_start[lev - 1]));
+    }
+done:
+    (void)hipStreamSynchronize(st);
+    for (void* p : {static_cast<void*>(d_th), static_cast<void*>(vst), static_cast<void*>(F), static_cast<void*>(gram),
+                    static_cast<void*>(dval), static_cast<void*>(scratch), static_cast<void*>(PV),
+                    static_cast<void*>(PS), static_cast<void*>(PVAR), static_cast<void*>(d_px),
+                    static_cast<void*>(d_py), static_cast<void*>(d_mean), static_cast<void*>(d_var),
+                    static_cast<void*>(out1), static_cast<void*>(status), static_cast<void*>(d_plo),
+                    static_cast<void*>(d_phi), static_cast<void*>(d_sleaf), static_cast<void*>(d_perm),
+                    static_cast<void*>(d_pleaf), static_cast<void*>(d_pchain)})
+        if (p) (void)hipFree(p);
+    return rc;
 }

@@ -31,3 +31,10 @@ int build_host_tree(const double* x, const double* y, const double* z, int64_t n
                     int M, double offset, const double* domain4, HostTree& t, std::string& err);
 
 }  // namespace mra
+
+namespace mra {
+// Leaf (global level-order index) of each location by descent from the root;
+// MRA_EDOMAIN for a location outside the root region.
+int locate_leaves(const HostTree& t, const double* x, const double* y, int64_t n, std::vector<int64_t>& leaf,
+                  std::string& err);
+}  // namespace mra

@@ -51,6 +51,19 @@ struct KArgs {
     int level;                // level (1-based) of this launch
     double* out;              // final: loglik per theta
     double n_used;
+    // prediction (one theta): points grouped by leaf
+    const double* px;
+    const double* py;
+    const int64_t* pred_lo;   // per region: first prediction point of its subtree
+    const int64_t* pred_hi;
+    const int64_t* pred_leaf; // per point: global index of its leaf
+    const int64_t* pred_perm; // per point: index in the caller's order
+    double* PV;               // npred x WFs: whitened prior rows of the points
+    double* PS;               // npred x WFs: H (columns of the levels) and the mean (last column)
+    double* PVAR;             // npred: variance
+    int64_t npred;
+    double* mean_out;
+    double* var_out;
 };
 
 }  // namespace mra

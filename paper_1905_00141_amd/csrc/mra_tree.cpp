@@ -170,4 +170,24 @@ int build_host_tree(const double* x, const double* y, const double* z, int64_t n
     return MRA_OK;
 }
 
+int locate_leaves(const HostTree& t, const double* x, const double* y, int64_t n, std::vector<int64_t>& leaf,
+                  std::string& err) {
+    leaf.assign(n, 0);
+    const Box root{t.box[0], t.box[1], t.box[2], t.box[3]};
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(x[i] >= root.xlo && x[i] < root.xhi && y[i] >= root.ylo && y[i] < root.yhi)) {
+            err = "prediction location " + std::to_string(i) + " lies outside the root region";
+            return MRA_EDOMAIN;
+        }
+        int64_t k = 0;
+        for (int m = 0; m + 1 < t.M; ++m) {
+            const int64_t g = t.lvl_start[m] + k;
+            const Box b{t.box[4 * g], t.box[4 * g + 1], t.box[4 * g + 2], t.box[4 * g + 3]};
+            k = t.J * k + which_child(b, t.J, x[i], y[i]);
+        }
+        leaf[i] = t.lvl_start[t.M - 1] + k;
+    }
+    return MRA_OK;
+}
+
 }  // namespace mra
