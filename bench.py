@@ -5,7 +5,7 @@
 A step is one mra_loglik call that evaluates the MRA log-likelihood of all
 covariance-parameter vectors of the batch (64 by default) over the whole tree:
 prior on every level, finest-level factors, folds to the root, final sums.
-Workload (BASELINE configuration "batched"): n = 2^20 locations from a seeded
+Workload (batched evaluation at n = 2^20): n = 2^20 locations from a seeded
 16-component Gaussian mixture on [0,1]^2, RFF Matern-3/2 values, M = 9, J = 4,
 r = 64, theta = 8 ranges (0.02..0.3) x 8 nuggets (1e-3..1e-1), FP64.
 Inputs (tree, theta) are resident in HBM before the timed region.
@@ -88,6 +88,29 @@ def cpu_baseline(cfg, theta, budget_s=25.0):
     }
 
 
+def kernel_source_digest():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1905_00141_amd", "csrc", "mra_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(name, level):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy kernel), or None when the
+    kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256_16") != kernel_source_digest():
+        return None
+    for k in rec.get("kernels", []):
+        if k["name"] == name and k["level"] == level:
+            return {"bytes_per_launch": k["bytes_per_launch"], "source": rec["summary"]}
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,10 +119,13 @@ def main():
     ap.add_argument("--n-theta", type=int, default=64, help="must be a square (ranges x nuggets)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scale", type=int, default=0, help="shrink n by 4^scale and M by scale (quick runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the run, launch a fill and a plain FP64 copy kernel of MIB MiB each: the "
+                         "reference that scales hardware byte counters (FETCH_SIZE, WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
-              "(this build runs on a single MI355X; see DESIGN.md for the sharding design)", file=sys.stderr)
+              "(the library runs on a single MI355X)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -198,6 +224,17 @@ def main():
         },
         "roofline": roof,
     }
+    traffic = measured_traffic(dom["name"], dom["level"])
+    if traffic is not None:
+        roof["traffic"] = traffic["bytes_per_launch"]
+        roof["traffic_source"] = traffic["source"]
+    if args.copy_calibration:
+        nel = (args.copy_calibration << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: fill and copy of {args.copy_calibration} MiB")
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, cfg["theta"][0])
     print(json.dumps(res), flush=True)
