@@ -98,6 +98,18 @@ int mra_loglik(const mra_tree *tree, int family, double nu, const double *theta,
                double *loglik, void *stream);
 
 /*
+ * The two terms of the log-likelihood per theta, besides loglik itself:
+ *   loglik = -1/2 [ n_used log(2 pi) + logdet + quad ],
+ *   logdet = log det (Sigma_MRA + tau I),  quad = z^T (Sigma_MRA + tau I)^{-1} z.
+ * Since Sigma_MRA scales with the sill, at fixed range and nugget-to-sill
+ * ratio the log-likelihood is maximised over the sill in closed form from
+ * these two terms (sill_hat = sill * quad / n_used).  logdet and quad are
+ * optional (NULL); memory space, stream and errors as for mra_loglik.
+ */
+int mra_loglik_terms(const mra_tree *tree, int family, double nu, const double *theta, int64_t B,
+                     double *loglik, double *logdet, double *quad, void *stream);
+
+/*
  * Kriging (prediction mode, Sec. 2.2): posterior mean and variance of the
  * latent process X (no nugget) at np locations given the tree's observations.
  * Each location joins the finest-level region that contains it.

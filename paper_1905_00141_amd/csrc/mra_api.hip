@@ -35,9 +35,7 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st);
 }  // namespace mra
 
-using namespace mra;
-
-namespace {
+namespace mra {
 
 thread_local std::string g_err;
 
@@ -45,6 +43,36 @@ int fail(int code, const std::string& msg) {
     g_err = msg;
     return code;
 }
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice;
+}
+
+int check_device() {
+    int dev = 0, cnt = 0;
+    if (hipGetDeviceCount(&cnt) != hipSuccess || cnt == 0) {
+        (void)hipGetLastError();
+        return fail(MRA_EDEVICE, "no HIP device");
+    }
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MRA_EDEVICE, "hipGetDevice failed");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(MRA_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(MRA_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    return MRA_OK;
+}
+
+}  // namespace mra
+
+using namespace mra;
+
+namespace {
 
 // Largest observation count a region may hold and still fold in observation
 // space (its scratch matrix is that count squared).  MRA_FACTOR_FOLD_MAX in
@@ -63,16 +91,6 @@ int upload(T** dst, const std::vector<T>& v) {
     if (!v.empty() && hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
         return MRA_EDEVICE;
     return MRA_OK;
-}
-
-bool is_device_ptr(const void* p) {
-    if (!p) return false;
-    hipPointerAttribute_t at;
-    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
-        (void)hipGetLastError();
-        return false;
-    }
-    return at.type == hipMemoryTypeDevice;
 }
 
 int64_t ipow_h(int64_t b, int e) {
@@ -376,20 +394,6 @@ extern "C" const char* mra_last_error(void) { return g_err.c_str(); }
 
 extern "C" void mra_free_tree(mra_tree* t) { delete t; }
 
-static int check_device() {
-    int dev = 0, cnt = 0;
-    if (hipGetDeviceCount(&cnt) != hipSuccess || cnt == 0) {
-        (void)hipGetLastError();
-        return fail(MRA_EDEVICE, "no HIP device");
-    }
-    if (hipGetDevice(&dev) != hipSuccess) return fail(MRA_EDEVICE, "hipGetDevice failed");
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(MRA_EDEVICE, "hipGetDeviceProperties failed");
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        return fail(MRA_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
-    return MRA_OK;
-}
-
 extern "C" int mra_build_tree(const double* x, const double* y, const double* z, int64_t n, int J, int r, int M,
                               double offset, uint32_t flags, const double* domain4, mra_tree** out) {
     if (!out) return fail(MRA_EINVAL, "out is NULL");
@@ -593,15 +597,15 @@ static hipError_t enqueue_fold(const mra_tree* t, const Plan& pl, KArgs a, int m
 // a call on a different stream first waits for the previous call's work.
 struct Workspace {
     double *vst = nullptr, *F = nullptr, *gram = nullptr, *dval = nullptr, *scratch = nullptr;
-    double *th = nullptr, *out = nullptr;
+    double *th = nullptr, *out = nullptr, *ld = nullptr, *q = nullptr;
     int* status = nullptr;
     int64_t Bc = 0, nslot = 0, scratch_per = 0, cap_B = 0;
     bool mem_limited = false;  // Bc was capped by device memory, not by the request
     hipEvent_t done = nullptr;
     hipStream_t last = nullptr;
     bool used = false;
-    // captured graphs of whole evaluations, keyed by (theta, out, B, smooth, stream)
-    std::map<std::tuple<const void*, void*, int64_t, int, void*>, hipGraphExec_t> graphs;
+    // captured graphs of whole evaluations, keyed by (theta, out, logdet, quad, B, smooth, stream)
+    std::map<std::tuple<const void*, void*, void*, void*, int64_t, int, void*>, hipGraphExec_t> graphs;
     void drop_graphs() {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
         graphs.clear();
@@ -611,9 +615,10 @@ struct Workspace {
         drop_graphs();
         for (void* p : {static_cast<void*>(vst), static_cast<void*>(F), static_cast<void*>(gram),
                         static_cast<void*>(dval), static_cast<void*>(scratch), static_cast<void*>(th),
-                        static_cast<void*>(out), static_cast<void*>(status)})
+                        static_cast<void*>(out), static_cast<void*>(ld), static_cast<void*>(q),
+                        static_cast<void*>(status)})
             if (p) (void)hipFree(p);
-        vst = F = gram = dval = scratch = th = out = nullptr;
+        vst = F = gram = dval = scratch = th = out = ld = q = nullptr;
         status = nullptr;
         Bc = nslot = cap_B = 0;
         used = false;
@@ -664,7 +669,9 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
         !al(reinterpret_cast<void**>(&w.scratch), size_t(nslot) * scratch_per * 8) ||
         !al(reinterpret_cast<void**>(&w.status), size_t(capB) * sizeof(int)) ||
         !al(reinterpret_cast<void**>(&w.th), size_t(capB) * 3 * 8) ||
-        !al(reinterpret_cast<void**>(&w.out), size_t(capB) * 8)) {
+        !al(reinterpret_cast<void**>(&w.out), size_t(capB) * 8) ||
+        !al(reinterpret_cast<void**>(&w.ld), size_t(capB) * 8) ||
+        !al(reinterpret_cast<void**>(&w.q), size_t(capB) * 8)) {
         (void)hipGetLastError();
         w.release();
         return fail(MRA_ENOMEM, "device allocation of the evaluation workspace failed");
@@ -684,7 +691,7 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
 
 // Every launch of one evaluation of B parameter vectors (chunks of Bc).
 static hipError_t enqueue_loglik(const mra_tree* t, Workspace& w, KArgs a, const double* d_th, double* d_out,
-                                 int* status, int64_t B, hipStream_t st) {
+                                 double* d_ld, double* d_q, int* status, int64_t B, hipStream_t st) {
     const HostTree& h = t->h;
     const Plan& pl = t->lik;
     hipError_t e;
@@ -695,6 +702,8 @@ static hipError_t enqueue_loglik(const mra_tree* t, Workspace& w, KArgs a, const
         a.ntheta = nb;
         a.status = status + b0;
         a.out = d_out + b0;
+        a.out_ld = d_ld ? d_ld + b0 : nullptr;
+        a.out_q = d_q ? d_q + b0 : nullptr;
         if ((e = launch_fill(w.dval, int64_t(nb) * h.nreg, 0.0, st))) return e;
         if ((e = enqueue_prior(t, pl, a, nb, st))) return e;
         if ((e = enqueue_leaves(t, pl, a, nb, w.nslot, st))) return e;
@@ -712,8 +721,8 @@ static bool graphs_enabled() {
     return !(e && *e == '0');
 }
 
-extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double* theta, int64_t B,
-                          double* loglik, void* stream) {
+static int loglik_impl(const mra_tree* t, int family, double nu, const double* theta, int64_t B, double* loglik,
+                       double* logdet, double* quad, void* stream) {
     if (!t || !theta || !loglik || B < 1) return fail(MRA_EINVAL, "NULL argument or B < 1");
     int smooth = 0;
     int rc = smooth_of(family, nu, &smooth);
@@ -721,7 +730,8 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
     const HostTree& h = t->h;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const bool dev = is_device_ptr(theta);
-    if (dev != is_device_ptr(loglik)) return fail(MRA_EINVAL, "theta and loglik must be in the same memory space");
+    if (dev != is_device_ptr(loglik) || (logdet && dev != is_device_ptr(logdet)) || (quad && dev != is_device_ptr(quad)))
+        return fail(MRA_EINVAL, "theta, loglik, logdet and quad must be in the same memory space");
     if (!dev)
         for (int64_t b = 0; b < B; ++b)
             if (!theta_ok(theta + 3 * b))
@@ -734,6 +744,8 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
     if (w.used && w.last != st) (void)hipStreamWaitEvent(st, w.done, 0);
     double* d_th = dev ? const_cast<double*>(theta) : w.th;
     double* d_out = dev ? loglik : w.out;
+    double* d_ld = logdet ? (dev ? logdet : w.ld) : nullptr;
+    double* d_q = quad ? (dev ? quad : w.q) : nullptr;
     std::vector<int> hstatus;
     KArgs a = base_args(t, t->lik, smooth);
     a.vst = w.vst; a.F = w.F; a.gram = w.gram; a.dval = w.dval;
@@ -746,14 +758,15 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
     if (!dev) HIPCHK(hipMemcpyAsync(d_th, theta, 3 * B * 8, hipMemcpyHostToDevice, st));
     if (dev && st != nullptr && !profiling && graphs_enabled()) {
         // a repeated evaluation on the same buffers replays one captured graph
-        const auto key = std::make_tuple(static_cast<const void*>(theta), static_cast<void*>(loglik), B, smooth,
+        const auto key = std::make_tuple(static_cast<const void*>(theta), static_cast<void*>(loglik),
+                                         static_cast<void*>(logdet), static_cast<void*>(quad), B, smooth,
                                          static_cast<void*>(st));
         auto it = w.graphs.find(key);
         if (it == w.graphs.end()) {
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
             HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            const hipError_t ce = enqueue_loglik(t, w, a, d_th, d_out, w.status, B, st);
+            const hipError_t ce = enqueue_loglik(t, w, a, d_th, d_out, d_ld, d_q, w.status, B, st);
             const hipError_t ee = hipStreamEndCapture(st, &g);
             HIPCHK(ce);
             HIPCHK(ee);
@@ -764,13 +777,15 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
         }
         HIPCHK(hipGraphLaunch(it->second, st));
     } else {
-        HIPCHK(enqueue_loglik(t, w, a, d_th, d_out, w.status, B, st));
+        HIPCHK(enqueue_loglik(t, w, a, d_th, d_out, d_ld, d_q, w.status, B, st));
     }
     (void)hipEventRecord(w.done, st);
     w.last = st;
     w.used = true;
     if (!dev) {
         HIPCHK(hipMemcpyAsync(loglik, d_out, B * 8, hipMemcpyDeviceToHost, st));
+        if (logdet) HIPCHK(hipMemcpyAsync(logdet, d_ld, B * 8, hipMemcpyDeviceToHost, st));
+        if (quad) HIPCHK(hipMemcpyAsync(quad, d_q, B * 8, hipMemcpyDeviceToHost, st));
         hstatus.resize(B);
         HIPCHK(hipMemcpyAsync(hstatus.data(), w.status, B * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -785,6 +800,16 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
     }
 done:
     return rc;
+}
+
+extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double* theta, int64_t B,
+                          double* loglik, void* stream) {
+    return loglik_impl(t, family, nu, theta, B, loglik, nullptr, nullptr, stream);
+}
+
+extern "C" int mra_loglik_terms(const mra_tree* t, int family, double nu, const double* theta, int64_t B,
+                                double* loglik, double* logdet, double* quad, void* stream) {
+    return loglik_impl(t, family, nu, theta, B, loglik, logdet, quad, stream);
 }
 
 // ---------------------------------------------------------------- kriging

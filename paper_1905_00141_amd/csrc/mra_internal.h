@@ -33,6 +33,12 @@ int build_host_tree(const double* x, const double* y, const double* z, int64_t n
 }  // namespace mra
 
 namespace mra {
+// Error reporting and pointer classification shared by the library's entry
+// points: fail() records the thread-local message of mra_last_error.
+int fail(int code, const std::string& msg);
+bool is_device_ptr(const void* p);
+int check_device();
+
 // Leaf (global level-order index) of each location by descent from the root;
 // MRA_EDOMAIN for a location outside the root region.
 int locate_leaves(const HostTree& t, const double* x, const double* y, int64_t n, std::vector<int64_t>& leaf,

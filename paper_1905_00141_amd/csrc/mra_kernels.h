@@ -50,6 +50,8 @@ struct KArgs {
     int64_t ntasks;           // regions per theta
     int level;                // level (1-based) of this launch
     double* out;              // final: loglik per theta
+    double* out_ld;           // final (optional): sum of log-determinants per theta
+    double* out_q;            // final (optional): quadratic form per theta
     double n_used;
     // prediction (one theta): points grouped by leaf
     const double* px;

@@ -1089,8 +1089,11 @@ __global__ void __launch_bounds__(NT) k_final(KArgs a, int64_t nreg, int root_gr
         const double* thp = a.theta + 3 * th;
         const bool ok = thp[0] > 0.0 && thp[1] > 0.0 && thp[2] > 0.0 && thp[0] < 1.0 / 0.0 && thp[1] < 1.0 / 0.0 &&
                         thp[2] < 1.0 / 0.0;
-        if (a.status[th] != 0 || !ok) ll = __builtin_nan("");
+        const bool bad = a.status[th] != 0 || !ok;
+        if (bad) ll = __builtin_nan("");
         a.out[th] = ll;
+        if (a.out_ld) a.out_ld[th] = bad ? __builtin_nan("") : dsum;
+        if (a.out_q) a.out_q[th] = bad ? __builtin_nan("") : q;
     }
 }
 

@@ -21,8 +21,12 @@ MRA_DEVICE_PTRS = 1 << 0
 MRA_FOLD_GRAM = 1 << 4
 MRA_FOLD_FACTOR = 1 << 5
 
-EXPORTED = ["mra_build_tree", "mra_loglik", "mra_predict", "mra_free_tree", "mra_last_error",
-            "mra_tree_info", "mra_tree_arrays", "mra_profile_enable", "mra_profile_read"]
+EXPORTED = ["mra_build_tree", "mra_loglik", "mra_loglik_terms", "mra_predict", "mra_free_tree", "mra_last_error",
+            "mra_tree_info", "mra_tree_arrays", "mra_profile_enable", "mra_profile_read",
+            "mra_mlp_create", "mra_mlp_set_scaling", "mra_mlp_forward", "mra_mlp_loss_grad",
+            "mra_mlp_train_step", "mra_mlp_get_params", "mra_mlp_free"]
+MLP_WIDTH = 128
+MLP_NPARAM = 50177
 
 
 class MraInfo(C.Structure):
@@ -53,6 +57,8 @@ def load_library(path: str = LIB_PATH):
     L.mra_build_tree.restype = C.c_int
     L.mra_loglik.argtypes = [vp, C.c_int, C.c_double, pd, i64, pd, vp]
     L.mra_loglik.restype = C.c_int
+    L.mra_loglik_terms.argtypes = [vp, C.c_int, C.c_double, pd, i64, pd, pd, pd, vp]
+    L.mra_loglik_terms.restype = C.c_int
     L.mra_predict.argtypes = [vp, C.c_int, C.c_double, pd, pd, pd, i64, pd, pd, vp]
     L.mra_predict.restype = C.c_int
     L.mra_free_tree.argtypes = [vp]
@@ -67,6 +73,21 @@ def load_library(path: str = LIB_PATH):
     L.mra_profile_enable.restype = C.c_int
     L.mra_profile_read.argtypes = [C.POINTER(KernelStat), C.c_int, C.POINTER(C.c_int)]
     L.mra_profile_read.restype = C.c_int
+    f32 = C.c_float
+    L.mra_mlp_create.argtypes = [vp, C.POINTER(vp)]
+    L.mra_mlp_create.restype = C.c_int
+    L.mra_mlp_set_scaling.argtypes = [vp, pd, pd, C.c_double, C.c_double]
+    L.mra_mlp_set_scaling.restype = C.c_int
+    L.mra_mlp_forward.argtypes = [vp, vp, i64, pd, vp]
+    L.mra_mlp_forward.restype = C.c_int
+    L.mra_mlp_loss_grad.argtypes = [vp, vp, pd, i64, vp, pd, vp]
+    L.mra_mlp_loss_grad.restype = C.c_int
+    L.mra_mlp_train_step.argtypes = [vp, vp, pd, i64, f32, f32, f32, f32, pd, vp]
+    L.mra_mlp_train_step.restype = C.c_int
+    L.mra_mlp_get_params.argtypes = [vp, vp]
+    L.mra_mlp_get_params.restype = C.c_int
+    L.mra_mlp_free.argtypes = [vp]
+    L.mra_mlp_free.restype = None
     return L
 
 
@@ -171,6 +192,21 @@ class Tree:
                                _stream_ptr(stream)))
         return res
 
+    def loglik_terms(self, theta, family="matern", nu=0.5, stream=None):
+        """(loglik, logdet, quad) per theta; host arrays or device tensors like loglik."""
+        if isinstance(theta, np.ndarray) or not hasattr(theta, "data_ptr"):
+            th = np.ascontiguousarray(np.atleast_2d(theta), dtype=np.float64)
+            B = th.shape[0]
+            ll, ld, q = np.empty(B), np.empty(B), np.empty(B)
+        else:
+            import torch
+            th = theta
+            B = th.shape[0]
+            ll, ld, q = (torch.empty(B, dtype=torch.float64, device=th.device) for _ in range(3))
+        _check(_lib.mra_loglik_terms(self._h, family_code(family), float(nu), _ptr(th), B, _ptr(ll), _ptr(ld),
+                                     _ptr(q), _stream_ptr(stream)))
+        return ll, ld, q
+
     def predict(self, theta, px, py, family="matern", nu=0.5, stream=None):
         th = np.ascontiguousarray(theta, dtype=np.float64)
         dev = not isinstance(px, np.ndarray)
@@ -186,3 +222,78 @@ class Tree:
         _check(_lib.mra_predict(self._h, family_code(family), float(nu), _ptr(th), _ptr(px), _ptr(py), len(px),
                                 _ptr(mean), _ptr(var), _stream_ptr(stream)))
         return mean, var
+
+
+def _ptr32(a):
+    """Address of a contiguous float32 NumPy array or torch tensor."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags.c_contiguous and a.dtype == np.float32
+        return a.ctypes.data
+    assert a.is_contiguous() and str(a.dtype) == "torch.float32"
+    return a.data_ptr()
+
+
+class Mlp:
+    """Handle on the library's FP32 surrogate network (include/mra_mlp.h).
+
+    x: (B, 3) float32 (log sill, log range, log nugget); y: (B,) float64.
+    NumPy arrays (host) or torch CUDA tensors (device), not mixed."""
+
+    def __init__(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (MLP_NPARAM,):
+            raise ValueError(f"params must hold {MLP_NPARAM} values")
+        h = C.c_void_p()
+        _check(_lib.mra_mlp_create(p.ctypes.data, C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.mra_mlp_free(h)
+            self._h = None
+
+    def set_scaling(self, x_lo, x_hi, y_mean, y_std):
+        lo = np.ascontiguousarray(x_lo, dtype=np.float64)
+        hi = np.ascontiguousarray(x_hi, dtype=np.float64)
+        _check(_lib.mra_mlp_set_scaling(self._h, lo.ctypes.data, hi.ctypes.data, float(y_mean), float(y_std)))
+
+    def forward(self, x, out=None, stream=None):
+        B = x.shape[0]
+        if out is None:
+            if isinstance(x, np.ndarray):
+                out = np.empty(B)
+            else:
+                import torch
+                out = torch.empty(B, dtype=torch.float64, device=x.device)
+        _check(_lib.mra_mlp_forward(self._h, _ptr32(x), B, _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def loss_grad(self, x, y, stream=None):
+        B = x.shape[0]
+        if isinstance(x, np.ndarray):
+            g, loss = np.empty(MLP_NPARAM, dtype=np.float32), np.empty(1)
+        else:
+            import torch
+            g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=x.device)
+            loss = torch.empty(1, dtype=torch.float64, device=x.device)
+        _check(_lib.mra_mlp_loss_grad(self._h, _ptr32(x), _ptr(y), B, _ptr32(g), _ptr(loss), _stream_ptr(stream)))
+        return loss, g
+
+    def train_step(self, x, y, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        B = x.shape[0]
+        if isinstance(x, np.ndarray):
+            loss = np.empty(1)
+        else:
+            import torch
+            loss = torch.empty(1, dtype=torch.float64, device=x.device)
+        _check(_lib.mra_mlp_train_step(self._h, _ptr32(x), _ptr(y), B, lr, beta1, beta2, eps, _ptr(loss),
+                                       _stream_ptr(stream)))
+        return loss
+
+    def params(self):
+        p = np.empty(MLP_NPARAM, dtype=np.float32)
+        _check(_lib.mra_mlp_get_params(self._h, p.ctypes.data))
+        return p

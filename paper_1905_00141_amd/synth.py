@@ -151,3 +151,36 @@ def small_case(seed, n, J=4, r=16, M=3, cluster=False, nu=0.5):
     rng = np.random.default_rng(seed + 7)
     z = rng.standard_normal(n)
     return dict(x=x, y=y, z=z, J=J, r=r, M=M, nu=nu)
+
+
+# ---------------------------------------------------------------------------
+# Surrogate network: initial parameters and the training design.
+# ---------------------------------------------------------------------------
+
+MLP_WIDTH = 128
+MLP_LAYERS = [(128, 3), (128, 128), (128, 128), (128, 128), (1, 128)]  # (fan_out, fan_in)
+
+
+def mlp_init(seed):
+    """Initial parameters (float32, the library's order: W1, b1, ..., w5, b5):
+    weights uniform in +-sqrt(6 / (fan_in + fan_out)), biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fo, fi in MLP_LAYERS:
+        lim = np.sqrt(6.0 / (fi + fo))
+        parts.append(rng.uniform(-lim, lim, size=fo * fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def sobol_box(n, lo, hi, seed):
+    """n scrambled Sobol points in the box [lo, hi] (per coordinate)."""
+    from scipy.stats import qmc
+    s = qmc.Sobol(d=len(lo), scramble=True, seed=seed).random(n)
+    lo, hi = np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
+    return lo + s * (hi - lo)
+
+
+# Config 5: the surrogate's log-parameter box (log alpha, log beta, log tau).
+SURROGATE_BOX_LO = np.log([0.25, 0.02, 1e-3])
+SURROGATE_BOX_HI = np.log([4.0, 0.3, 1e-1])
