@@ -119,6 +119,9 @@ def main():
     ap.add_argument("--n-theta", type=int, default=64, help="must be a square (ranges x nuggets)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scale", type=int, default=0, help="shrink n by 4^scale and M by scale (quick runs)")
+    ap.add_argument("--mle", action="store_true",
+                    help="also run the MLE searches on the same tree (32x32 profiled grid, Nelder-Mead without and "
+                         "with the surrogate trained on 2048 exact evaluations) and report exact-evaluation counts")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, launch a fill and a plain FP64 copy kernel of MIB MiB each: the "
                          "reference that scales hardware byte counters (FETCH_SIZE, WRITE_SIZE)")
@@ -235,6 +238,11 @@ def main():
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: fill and copy of {args.copy_calibration} MiB")
+    if args.mle:
+        from paper_1905_00141_amd import mle
+        t0 = time.time()
+        res["mle"] = mle.run(tree, cfg["family"], cfg["nu"], n_train=2048, train_steps=3000, log=log)
+        res["mle"]["wall_s"] = time.time() - t0
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, cfg["theta"][0])
     print(json.dumps(res), flush=True)

@@ -14,12 +14,12 @@ alpha_hat = Q / n.  The searches therefore run in the plane (log beta, log lam).
 
 Three searches, each counting exact evaluations:
   * grid: the plain 32 x 32 grid over (beta, lam), log-spaced;
-  * compass: a derivative-free pattern search on exact values from the centre
-    of the box (the method without the surrogate);
+  * local: a derivative-free Nelder-Mead search on exact values from the
+    centre of the box (the method without the surrogate);
   * surrogate: the network (include/mra_mlp.h) is trained on exact
     log-likelihoods at Sobol points of the (log alpha, log beta, log tau) box,
-    its maximum over a dense grid is the proposal, and the same pattern search
-    on exact values starts there with a finer step.
+    its maximum over a dense grid is the proposal, and the same Nelder-Mead
+    search on exact values starts there with a smaller simplex.
 The exact MRA stays the judge of every reported value.
 
 This module is orchestration only: every log-likelihood and every network
@@ -115,6 +115,49 @@ def compass_search(obj: ExactObjective, x0, step, min_step=1e-3, max_evals=400):
     return x, fx
 
 
+def nelder_mead(obj, x0, step, tol=0.02, max_evals=400):
+    """Nelder-Mead simplex search (Nelder & Mead, 1965) maximising the exact
+    objective in the box (points are clipped into it).  Standard coefficients:
+    reflection 1, expansion 2, contraction 1/2, shrink 1/2.  Stops when the
+    simplex's values span less than tol nats or the budget is spent."""
+    lo, hi = box2()
+    x0 = np.clip(np.asarray(x0, dtype=np.float64), lo, hi)
+    step = np.asarray(step, dtype=np.float64)
+    S = [x0]
+    for d in (np.array([step[0], 0.0]), np.array([0.0, step[1]])):
+        v = np.clip(x0 + d, lo, hi)
+        if np.allclose(v, x0):  # clipped onto x0 at a face of the box: step the other way
+            v = np.clip(x0 - d, lo, hi)
+        S.append(v)
+    S = np.array(S)
+    F = obj(S)
+    while obj.evals < max_evals:
+        o = np.argsort(-F)
+        S, F = S[o], F[o]
+        if F[0] - F[-1] < tol:
+            break
+        c = S[:-1].mean(axis=0)
+        xr = np.clip(c + (c - S[-1]), lo, hi)
+        fr = float(obj(xr)[0])
+        if fr > F[0]:
+            xe = np.clip(c + 2.0 * (c - S[-1]), lo, hi)
+            fe = float(obj(xe)[0])
+            S[-1], F[-1] = (xe, fe) if fe > fr else (xr, fr)
+        elif fr > F[-2]:
+            S[-1], F[-1] = xr, fr
+        else:
+            inside = fr <= F[-1]
+            xc = np.clip(c + 0.5 * ((S[-1] if inside else xr) - c), lo, hi)
+            fc = float(obj(xc)[0])
+            if fc > max(F[-1], fr if not inside else -np.inf):
+                S[-1], F[-1] = xc, fc
+            else:
+                S[1:] = S[0] + 0.5 * (S[1:] - S[0])
+                F[1:] = obj(S[1:])
+    i = int(np.argmax(F))
+    return S[i], float(F[i])
+
+
 def train_surrogate(tree: mra.Tree, n_train=2048, seed=5, steps=3000, lr=3e-3, family="matern", nu=1.5,
                     log=None):
     """Exact log-likelihoods at n_train Sobol points of the log box, then
@@ -163,13 +206,13 @@ def run(tree: mra.Tree, family="matern", nu=1.5, n_train=2048, grid_k=32, seed=5
     xg, fg = grid_search(g, grid_k)
 
     c = ExactObjective(tree, family, nu)
-    xc, fc = compass_search(c, (lo + hi) / 2, width / 4)
+    xc, fc = nelder_mead(c, (lo + hi) / 2, width / 4)
 
     net, n_tr = train_surrogate(tree, n_train, seed, train_steps, family=family, nu=nu, log=log)
     s = ExactObjective(tree, family, nu)
     x0 = surrogate_proposal(net)
     f0 = float(s(x0)[0])
-    xs, fs = compass_search(s, x0, width / 32)
+    xs, fs = nelder_mead(s, x0, width / 32)
 
     best = max(fg, fc, fs)
     target = best - 0.5
@@ -177,13 +220,13 @@ def run(tree: mra.Tree, family="matern", nu=1.5, n_train=2048, grid_k=32, seed=5
         "best_loglik": best,
         "grid": {"evals": g.evals, "evals_to_mle": g.evals if fg >= target else None, "loglik": fg,
                  "beta": math.exp(xg[0]), "lam": math.exp(xg[1]), "alpha": g.alpha_hat(xg)},
-        "compass": {"evals": c.evals, "evals_to_mle": c.evals_to_reach(target), "loglik": fc,
+        "local": {"evals": c.evals, "evals_to_mle": c.evals_to_reach(target), "loglik": fc,
                     "beta": math.exp(xc[0]), "lam": math.exp(xc[1])},
         "surrogate": {"train_evals": n_tr, "search_evals": s.evals, "evals_to_mle": s.evals_to_reach(target),
                       "proposal_loglik": f0, "loglik": fs, "beta": math.exp(xs[0]), "lam": math.exp(xs[1]),
                       "proposal_beta": math.exp(x0[0]), "proposal_lam": math.exp(x0[1])},
     }
     if log:
-        log(f"[mle] grid {grid_k}x{grid_k}: {g.evals} evals, best {fg:.3f}; compass: {c.evals} evals, best {fc:.3f}; "
+        log(f"[mle] grid {grid_k}x{grid_k}: {g.evals} evals, best {fg:.3f}; local search: {c.evals} evals, best {fc:.3f}; "
             f"surrogate: proposal {f0:.3f}, {s.evals} search evals, best {fs:.3f}")
     return res

@@ -45,3 +45,19 @@ def test_grid_order_and_count():
     obj = Quadratic(lo + 0.5 * (hi - lo))
     x, f = mle.grid_search(obj, 8)
     assert obj.evals == 64 and f == obj.best
+
+
+def test_nelder_mead_converges_and_counts():
+    lo, hi = mle.box2()
+    xs = lo + np.array([0.7, 0.25]) * (hi - lo)
+    obj = Quadratic(xs)
+    x, fx = mle.nelder_mead(obj, (lo + hi) / 2, (hi - lo) / 4, tol=1e-6)
+    assert fx > -1e-3 and np.allclose(x, xs, atol=0.01)
+    assert obj.evals < 150 and obj.evals_to_reach(-0.5) < obj.evals
+
+
+def test_nelder_mead_from_a_face_of_the_box():
+    lo, hi = mle.box2()
+    obj = Quadratic(lo + np.array([0.5, 0.5]) * (hi - lo))
+    x, fx = mle.nelder_mead(obj, hi, (hi - lo) / 8, tol=1e-6)
+    assert fx > -1e-3
