@@ -148,6 +148,35 @@ int mra_tree_arrays(const mra_tree *tree, double *x, double *y, double *z, int64
                     int64_t *leaf_off);
 
 /*
+ * Execution plan (scheduling only: results change by rounding at most).
+ * Each region above the finest level folds either in observation space
+ * (regions whose subtree holds few observations) or in knot space; leaves
+ * and small folds of up to small_max rows run on one-wave finishers, larger
+ * ones on workgroup kernels.
+ *
+ * mra_autotune times one evaluation of a host sample theta (B x 3) under
+ * candidate plans -- per level, the observation-space threshold in
+ * {0, 64, ..., 768}, then small_max in {64, 32, 16} -- keeps each choice that
+ * is at least 2 % faster, installs the best plan in the tree and reports it.
+ * mra_set_plan installs a plan directly (fold_max: M - 1 entries for levels
+ * 1 .. M-1, -1 = the default rule; or NULL), e.g. one cached from an earlier
+ * autotune.  Both drop the tree's evaluation workspace; they must not run
+ * concurrently with other calls on the same tree.  Trees built with
+ * MRA_FOLD_GRAM or MRA_FOLD_FACTOR cannot be tuned (MRA_EINVAL).
+ */
+typedef struct mra_tune_result {
+    int32_t levels;        /* M */
+    int32_t small_max;     /* 16, 32 or 64 */
+    int64_t fold_max[16];  /* [m - 1]: threshold of level m = 1 .. M-1 */
+    double ms_before;      /* one evaluation of the sample with the plan on entry */
+    double ms_after;       /* ... with the plan installed */
+    int32_t trials;        /* plans timed */
+} mra_tune_result;
+
+int mra_autotune(mra_tree *tree, int family, double nu, const double *theta, int64_t B, mra_tune_result *out);
+int mra_set_plan(mra_tree *tree, const int64_t *fold_max, int small_max);
+
+/*
  * Optional per-launch timing, for measurement.  While enabled, every kernel
  * launch of mra_loglik is bracketed by HIP events on the caller's stream, or,
  * with only_kernel non-NULL, only the launches of that kernel at only_level

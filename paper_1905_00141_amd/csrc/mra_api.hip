@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <chrono>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -136,8 +137,18 @@ struct Plan {
     }
 };
 
+// Execution choices that change which kernel handles a region, never the
+// result beyond rounding: the largest subtree (observations) folded in
+// observation space per level (-1: the default rule) and the largest leaf or
+// fold handled by the one-wave finishers (16, 32 or 64).
+struct PlanOpts {
+    std::vector<int64_t> fold_max;  // index m = 1 .. M-1
+    int small_max = 64;
+};
+
 struct mra_tree {
     HostTree h;
+    PlanOpts opts;
     int device = 0;
     uint32_t flags = 0;
     double *d_x = nullptr, *d_y = nullptr, *d_z = nullptr, *d_box = nullptr;
@@ -210,7 +221,8 @@ static void plan_flops(const HostTree& h, Plan& t) {
 // beyond those holding observations (prediction points); gram_only forces
 // every fold into knot space.
 static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const std::vector<int64_t>* extra_count,
-                     Plan& t, std::string& err) {
+                     const PlanOpts* opts, Plan& t, std::string& err) {
+    const int64_t smax = opts ? opts->small_max : 64;
     const int M = h.M, P = h.P;
     t.form.assign(h.nreg, FOLD_FACTOR);
     t.vst_off.assign(h.nreg, -1);
@@ -221,9 +233,12 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
     for (int q = 0; q < 3; ++q) t.fsmall_tasks[q].assign(M, {});
     int64_t vo = 0, go = 0;
     for (int m = 1; m < M; ++m) {
-        const int64_t thr = (gram_only || (flags & MRA_FOLD_GRAM)) ? 0
-                            : (flags & MRA_FOLD_FACTOR) ? 4096
-                            : std::min<int64_t>(int64_t(m - 1) * P + 1, factor_fold_max());
+        int64_t thr = (gram_only || (flags & MRA_FOLD_GRAM)) ? 0
+                      : (flags & MRA_FOLD_FACTOR) ? 4096
+                      : std::min<int64_t>(int64_t(m - 1) * P + 1, factor_fold_max());
+        if (!gram_only && !(flags & (MRA_FOLD_GRAM | MRA_FOLD_FACTOR)) && opts && m < int64_t(opts->fold_max.size()) &&
+            opts->fold_max[m] >= 0)
+            thr = opts->fold_max[m];
         const int64_t D = int64_t(m) * P + 1;
         for (int64_t g = h.lvl_start[m - 1]; g < h.lvl_start[m]; ++g) {
             const int64_t np = h.obs_hi[g] - h.obs_lo[g];
@@ -235,9 +250,9 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
             if (np == 0) continue;             // prior only (prediction points below)
             if (np <= thr) {
                 t.form[g] = FOLD_FACTOR;
-                if (np <= 16) t.fsmall_tasks[0][m].push_back(int(g));
-                else if (np <= 32) t.fsmall_tasks[1][m].push_back(int(g));
-                else if (np <= 64) t.fsmall_tasks[2][m].push_back(int(g));
+                if (np <= 16 && np <= smax) t.fsmall_tasks[0][m].push_back(int(g));
+                else if (np <= 32 && np <= smax) t.fsmall_tasks[1][m].push_back(int(g));
+                else if (np <= 64 && np <= smax) t.fsmall_tasks[2][m].push_back(int(g));
                 else t.factor_tasks[m].push_back(int(g));
                 if (np > 64) t.scratch_fold = std::max(t.scratch_fold, np * np);
             } else {
@@ -256,9 +271,9 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
     t.gram_size = std::max<int64_t>(go, 1);
     for (int64_t g = h.lvl_start[M - 1]; g < h.lvl_start[M]; ++g) {
         const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
-        if (nc > 64) {
+        if (nc > smax) {
             t.leaf_tasks.push_back(int(g));
-            t.scratch_leaf = std::max(t.scratch_leaf, nc * nc);
+            if (nc > 64) t.scratch_leaf = std::max(t.scratch_leaf, nc * nc);
         } else if (nc > 32) {
             t.small_tasks[2].push_back(int(g));
         } else if (nc > 16) {
@@ -433,7 +448,8 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
         t->leaf_max = std::max(t->leaf_max, nc);
     }
     if (t->leaf_min == INT64_MAX) t->leaf_min = 0;
-    if ((rc = make_plan(h, flags, false, nullptr, t->lik, err))) {
+    t->opts.fold_max.assign(M, -1);
+    if ((rc = make_plan(h, flags, false, nullptr, &t->opts, t->lik, err))) {
         delete t;
         return fail(rc, err);
     }
@@ -812,6 +828,119 @@ extern "C" int mra_loglik_terms(const mra_tree* t, int family, double nu, const 
     return loglik_impl(t, family, nu, theta, B, loglik, logdet, quad, stream);
 }
 
+// ------------------------------------------------------------- autotuning
+
+// Rebuild the likelihood plan of a tree from its options; the evaluation
+// workspace (sized by the plan) and its captured graphs are dropped.
+static int replan(mra_tree* t) {
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        if (t->ws) static_cast<Workspace*>(t->ws)->release();
+    }
+    t->lik.~Plan();
+    new (&t->lik) Plan();
+    std::string err;
+    const int rc = make_plan(t->h, t->flags, false, nullptr, &t->opts, t->lik, err);
+    return rc ? fail(rc, err) : MRA_OK;
+}
+
+extern "C" int mra_set_plan(mra_tree* t, const int64_t* fold_max, int small_max) {
+    if (!t) return fail(MRA_EINVAL, "NULL tree");
+    if (small_max != 16 && small_max != 32 && small_max != 64) return fail(MRA_EINVAL, "small_max must be 16, 32 or 64");
+    const int M = t->h.M;
+    for (int m = 1; m < M; ++m) {
+        const int64_t v = fold_max ? fold_max[m - 1] : -1;
+        if (v > (int64_t(1) << 14)) return fail(MRA_EINVAL, "fold_max above 16384 observations");
+        t->opts.fold_max[m] = v < 0 ? -1 : v;
+    }
+    t->opts.small_max = small_max;
+    return replan(t);
+}
+
+// Form of every level-m region under a candidate threshold (to skip
+// candidates that change nothing).
+static std::vector<int8_t> level_forms(const HostTree& h, int m, int64_t thr) {
+    std::vector<int8_t> f;
+    for (int64_t g = h.lvl_start[m - 1]; g < h.lvl_start[m]; ++g) {
+        const int64_t np = h.obs_hi[g] - h.obs_lo[g];
+        f.push_back(np == 0 ? int8_t(2) : (np <= thr ? int8_t(FOLD_FACTOR) : int8_t(FOLD_GRAM)));
+    }
+    return f;
+}
+
+extern "C" int mra_autotune(mra_tree* t, int family, double nu, const double* theta, int64_t B,
+                            mra_tune_result* out) {
+    if (!t || !theta || !out || B < 1) return fail(MRA_EINVAL, "NULL argument or B < 1");
+    if (is_device_ptr(theta)) return fail(MRA_EINVAL, "theta must be host memory");
+    if (t->flags & (MRA_FOLD_GRAM | MRA_FOLD_FACTOR))
+        return fail(MRA_EINVAL, "the tree was built with a fixed fold form (MRA_FOLD_GRAM or MRA_FOLD_FACTOR)");
+    const HostTree& h = t->h;
+    const int M = h.M;
+    std::vector<double> ll(B);
+    int trials = 0;
+    // one evaluation of the sample, best of two (the first call after a
+    // plan change also allocates the workspace and is not timed)
+    auto time_plan = [&](double* ms) -> int {
+        int rc = loglik_impl(t, family, nu, theta, B, ll.data(), nullptr, nullptr, nullptr);
+        if (rc) return rc;
+        double best = 1e300;
+        for (int k = 0; k < 2; ++k) {
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = loglik_impl(t, family, nu, theta, B, ll.data(), nullptr, nullptr, nullptr);
+            if (rc) return rc;
+            best = std::min(best, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+        }
+        ++trials;
+        *ms = best;
+        return MRA_OK;
+    };
+    int rc;
+    double ms_before = 0.0;
+    if ((rc = time_plan(&ms_before))) return rc;
+    double ms_best = ms_before;
+    const int64_t cands[] = {0, 64, 128, 192, 256, 320, 384, 512, 768};
+    // levels bottom-up: the finest folds hold most of the work
+    for (int m = M - 1; m >= 1; --m) {
+        const int64_t keep = t->opts.fold_max[m];
+        const int64_t cur_thr = keep >= 0 ? keep : std::min<int64_t>(int64_t(m - 1) * h.P + 1, factor_fold_max());
+        std::vector<std::vector<int8_t>> seen{level_forms(h, m, cur_thr)};
+        int64_t best_v = keep;
+        for (int64_t c : cands) {
+            auto f = level_forms(h, m, c);
+            if (std::find(seen.begin(), seen.end(), f) != seen.end()) continue;
+            seen.push_back(f);
+            t->opts.fold_max[m] = c;
+            if ((rc = replan(t))) return rc;
+            double ms = 0.0;
+            if ((rc = time_plan(&ms))) return rc;
+            if (ms < 0.98 * ms_best) { ms_best = ms; best_v = c; }
+        }
+        t->opts.fold_max[m] = best_v;
+        if ((rc = replan(t))) return rc;
+    }
+    for (int sm : {32, 16}) {
+        const int keep = t->opts.small_max;
+        t->opts.small_max = sm;
+        if ((rc = replan(t))) return rc;
+        double ms = 0.0;
+        if ((rc = time_plan(&ms))) return rc;
+        if (ms < 0.98 * ms_best) ms_best = ms;
+        else t->opts.small_max = keep;
+    }
+    if ((rc = replan(t))) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->levels = M;
+    for (int m = 1; m < M && m <= 16; ++m) {
+        const int64_t v = t->opts.fold_max[m];
+        out->fold_max[m - 1] = v >= 0 ? v : std::min<int64_t>(int64_t(m - 1) * h.P + 1, factor_fold_max());
+    }
+    out->small_max = t->opts.small_max;
+    out->ms_before = ms_before;
+    out->ms_after = ms_best;
+    out->trials = trials;
+    return MRA_OK;
+}
+
 // ---------------------------------------------------------------- kriging
 
 extern "C" int mra_predict(const mra_tree* t, int family, double nu, const double* theta, const double* px,
@@ -869,7 +998,7 @@ extern "C" int mra_predict(const mra_tree* t, int family, double nu, const doubl
         }
     }
     Plan pl;
-    if ((rc = make_plan(h, t->flags, true, &pcount, pl, err))) return fail(rc, err);
+    if ((rc = make_plan(h, t->flags, true, &pcount, &t->opts, pl, err))) return fail(rc, err);
     std::vector<int> pred_leaf_tasks, pred_chain_tasks;
     for (int64_t g = h.lvl_start[M - 1]; g < h.lvl_start[M]; ++g)
         if (pcount[g] > 0) pred_leaf_tasks.push_back(int(g));

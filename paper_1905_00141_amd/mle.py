@@ -81,12 +81,16 @@ def box2():
     return np.log([BETA_LO, LAM_LO]), np.log([BETA_HI, LAM_HI])
 
 
-def grid_search(obj: ExactObjective, k=32):
+def grid_search(obj: ExactObjective, k=32, batch=64, log=None):
     lo, hi = box2()
     b = np.linspace(lo[0], hi[0], k)
     lam = np.linspace(lo[1], hi[1], k)
     X = np.array([(u, v) for u in b for v in lam])  # range-major, ratio-minor
-    f = obj(X)
+    f = np.empty(len(X))
+    for s in range(0, len(X), batch):
+        f[s:s + batch] = obj(X[s:s + batch])
+        if log:
+            log(f"[mle] grid: {min(s + batch, len(X))} of {len(X)} evaluated, best {obj.best:.3f}")
     i = int(np.argmax(f))  # first maximum in (range-major, ratio-minor) order
     return X[i], float(f[i])
 
@@ -168,6 +172,8 @@ def train_surrogate(tree: mra.Tree, n_train=2048, seed=5, steps=3000, lr=3e-3, f
     y = np.empty(n_train)
     for s in range(0, n_train, 64):  # batches of 64 parameter vectors per launch sequence
         y[s:s + 64] = tree.loglik(np.exp(X[s:s + 64]), family, nu)
+        if log:
+            log(f"[mle] surrogate training set: {min(s + 64, n_train)} of {n_train} exact evaluations")
     t_exact = time.time() - t0
     net = mra.Mlp(synth.mlp_init(seed))
     net.set_scaling(lo, hi, float(y.mean()), float(y.std()))
@@ -203,10 +209,12 @@ def run(tree: mra.Tree, family="matern", nu=1.5, n_train=2048, grid_k=32, seed=5
     lo, hi = box2()
     width = hi - lo
     g = ExactObjective(tree, family, nu)
-    xg, fg = grid_search(g, grid_k)
+    xg, fg = grid_search(g, grid_k, log=log)
 
     c = ExactObjective(tree, family, nu)
     xc, fc = nelder_mead(c, (lo + hi) / 2, width / 4)
+    if log:
+        log(f"[mle] local search without the surrogate: {c.evals} evals, best {fc:.3f}")
 
     net, n_tr = train_surrogate(tree, n_train, seed, train_steps, family=family, nu=nu, log=log)
     s = ExactObjective(tree, family, nu)

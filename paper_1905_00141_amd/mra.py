@@ -23,6 +23,7 @@ MRA_FOLD_FACTOR = 1 << 5
 
 EXPORTED = ["mra_build_tree", "mra_loglik", "mra_loglik_terms", "mra_predict", "mra_free_tree", "mra_last_error",
             "mra_tree_info", "mra_tree_arrays", "mra_profile_enable", "mra_profile_read",
+            "mra_autotune", "mra_set_plan",
             "mra_mlp_create", "mra_mlp_set_scaling", "mra_mlp_forward", "mra_mlp_loss_grad",
             "mra_mlp_train_step", "mra_mlp_get_params", "mra_mlp_free"]
 MLP_WIDTH = 128
@@ -34,6 +35,11 @@ class MraInfo(C.Structure):
                 ("J", C.c_int32), ("M", C.c_int32), ("r", C.c_int32), ("r_hat", C.c_int32), ("P", C.c_int32),
                 ("n_regions", C.c_int64), ("n_leaves", C.c_int64), ("leaf_min", C.c_int64),
                 ("leaf_max", C.c_int64), ("n_gram_regions", C.c_int64)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("small_max", C.c_int32), ("fold_max", C.c_int64 * 16),
+                ("ms_before", C.c_double), ("ms_after", C.c_double), ("trials", C.c_int32)]
 
 
 class KernelStat(C.Structure):
@@ -73,6 +79,10 @@ def load_library(path: str = LIB_PATH):
     L.mra_profile_enable.restype = C.c_int
     L.mra_profile_read.argtypes = [C.POINTER(KernelStat), C.c_int, C.POINTER(C.c_int)]
     L.mra_profile_read.restype = C.c_int
+    L.mra_autotune.argtypes = [vp, C.c_int, C.c_double, pd, i64, C.POINTER(TuneResult)]
+    L.mra_autotune.restype = C.c_int
+    L.mra_set_plan.argtypes = [vp, vp, C.c_int]
+    L.mra_set_plan.restype = C.c_int
     f32 = C.c_float
     L.mra_mlp_create.argtypes = [vp, C.POINTER(vp)]
     L.mra_mlp_create.restype = C.c_int
@@ -191,6 +201,23 @@ class Tree:
         _check(_lib.mra_loglik(self._h, family_code(family), float(nu), _ptr(th), B, _ptr(res),
                                _stream_ptr(stream)))
         return res
+
+    def autotune(self, theta, family="matern", nu=0.5):
+        """Time candidate execution plans on a host sample of theta and install the fastest."""
+        th = np.ascontiguousarray(np.atleast_2d(theta), dtype=np.float64)
+        r = TuneResult()
+        _check(_lib.mra_autotune(self._h, family_code(family), float(nu), th.ctypes.data, th.shape[0], C.byref(r)))
+        return dict(fold_max=[int(r.fold_max[i]) for i in range(r.levels - 1)], small_max=int(r.small_max),
+                    ms_before=r.ms_before, ms_after=r.ms_after, trials=int(r.trials))
+
+    def set_plan(self, fold_max=None, small_max=64):
+        """Install an execution plan (per-level fold thresholds, -1 = default rule)."""
+        if fold_max is None:
+            _check(_lib.mra_set_plan(self._h, None, int(small_max)))
+            return
+        fm = np.ascontiguousarray(fold_max, dtype=np.int64)
+        assert fm.shape == (self.info["M"] - 1,)
+        _check(_lib.mra_set_plan(self._h, fm.ctypes.data, int(small_max)))
 
     def loglik_terms(self, theta, family="matern", nu=0.5, stream=None):
         """(loglik, logdet, quad) per theta; host arrays or device tensors like loglik."""

@@ -232,3 +232,27 @@ def test_loglik_terms_and_scale_equivariance(mra, oracle):
     assert abs(ld[1] - (ld[0] + n * np.log(3.0))) <= 1e-10 * abs(ld[0]) + 1e-9
     assert abs(q[1] - q[0] / 3.0) <= 1e-10 * q[0]
     assert np.array_equal(t.loglik(th, "exp", 0.5), ll)
+
+
+def test_autotune_and_set_plan_keep_parity(mra, oracle):
+    """Autotuning changes which kernel handles a region, never the result:
+    after it (and after installing explicit plans) the log-likelihood still
+    matches the oracle, and the reported plan is the installed one."""
+    from paper_1905_00141_amd import synth
+    c = synth.small_case(77, 6000, J=4, r=30, M=5, cluster=True, nu=1.5)
+    t = mra.Tree(c["x"], c["y"], c["z"], J=4, r=30, M=5)
+    ref = oracle.Tree(c["x"], c["y"], c["z"], J=4, r=30, M=5).loglik(THETAS, oracle.MATERN, 1.5)
+    res = t.autotune(THETAS[:2], "matern", 1.5)
+    print("autotune", res)
+    assert len(res["fold_max"]) == 4 and res["small_max"] in (16, 32, 64) and res["trials"] >= 1
+    assert res["ms_after"] <= res["ms_before"]
+    assert np.all(_rel(t.loglik(THETAS, "matern", 1.5), ref) <= RTOL)
+    for fm, sm in [([0, 0, 0, 0], 16), ([768, 768, 768, 768], 32), ([-1, 64, 0, 256], 64), (None, 64)]:
+        t.set_plan(fm, sm)
+        got = t.loglik(THETAS, "matern", 1.5)
+        assert np.all(_rel(got, ref) <= RTOL), (fm, sm, _rel(got, ref))
+    with pytest.raises(mra.MraError):
+        t.set_plan(None, 48)
+    tg = mra.Tree(c["x"], c["y"], c["z"], J=4, r=30, M=5, flags=mra.MRA_FOLD_GRAM)
+    with pytest.raises(mra.MraError):
+        tg.autotune(THETAS[:1])
