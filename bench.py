@@ -119,6 +119,9 @@ def main():
     ap.add_argument("--n-theta", type=int, default=64, help="must be a square (ranges x nuggets)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scale", type=int, default=0, help="shrink n by 4^scale and M by scale (quick runs)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the execution-plan autotuner on 4 of the theta before timing (about a minute; "
+                         "on this workload it keeps the default plan)")
     ap.add_argument("--mle", action="store_true",
                     help="also run the MLE searches on the same tree (32x32 profiled grid, Nelder-Mead without and "
                          "with the surrogate trained on 2048 exact evaluations) and report exact-evaluation counts")
@@ -149,6 +152,11 @@ def main():
     info = tree.info
     log(f"[bench] tree built in {time.time() - t0:.1f} s: n_used {info['n_used']}, leaves "
         f"{info['leaf_min']}..{info['leaf_max']} obs, {info['n_gram_regions']} Gram-form regions")
+    tune = None
+    if args.autotune:
+        t0 = time.time()
+        tune = tree.autotune(cfg["theta"][::16], cfg["family"], cfg["nu"])
+        log(f"[bench] autotune in {time.time() - t0:.1f} s: {tune}")
     theta = torch.tensor(cfg["theta"], dtype=torch.float64, device=dev)
     B = theta.shape[0]
     out = torch.empty(B, dtype=torch.float64, device=dev)
@@ -224,6 +232,7 @@ def main():
             "r_hat": int(info["r_hat"]), "n_theta": int(B), "family": "matern", "nu": 1.5,
             "leaf_obs_min": int(info["leaf_min"]), "leaf_obs_max": int(info["leaf_max"]),
             "whole_path_tflops": all_flops * args.steps / elapsed / 1e12,
+            "plan": None if tune is None else {"fold_max": tune["fold_max"], "small_max": tune["small_max"]},
         },
         "roofline": roof,
     }

@@ -27,7 +27,8 @@ hipError_t launch_prior_finish(const KArgs& a, int grid, hipStream_t st);
 hipError_t launch_leaf(const KArgs& a, int grid, hipStream_t st);
 hipError_t launch_small(const KArgs& a, int nmax, int mode, int grid, hipStream_t st);
 hipError_t launch_fold_factor(const KArgs& a, int grid, hipStream_t st);
-hipError_t launch_fold_gram(const KArgs& a, int grid, hipStream_t st);
+hipError_t launch_gram_panel(const KArgs& a, int grid, hipStream_t st);
+hipError_t launch_gram_tile(const KArgs& a, hipStream_t st);
 hipError_t launch_final(const KArgs& a, int64_t nreg, int root_gram, hipStream_t st);
 hipError_t launch_pred_leaf(const KArgs& a, int grid, hipStream_t st);
 hipError_t launch_pred_fold(const KArgs& a, hipStream_t st);
@@ -124,7 +125,7 @@ struct Plan {
     std::vector<int*> d_prior, d_factor, d_gramt, d_fsmall[3];
     int *d_leaf = nullptr, *d_small[3] = {nullptr, nullptr, nullptr}, *d_chain_obs = nullptr;
     // algorithmic FP64 flops of one theta
-    std::vector<double> fl_chain, fl_pfin, fl_factor, fl_gram, fl_fsmall[3];
+    std::vector<double> fl_chain, fl_pfin, fl_factor, fl_gram, fl_gtile, fl_fsmall[3];
     double fl_chain_obs = 0.0, fl_leaf = 0.0, fl_small[3] = {0.0, 0.0, 0.0};
 
     ~Plan() {
@@ -169,8 +170,11 @@ struct mra_tree {
 //   prior finish, m      : (m-1) p^3 + p^3/3 + p^3/3 (SYRK, Cholesky, inverse)
 //   leaf finish          : (M-1) n^2 p + n^3/3 + n^2 ((M-1) p + 1)
 //   factor fold, m       : n^2 p + n^3/3 + n^2 ((m-1) p + 1)
-//   Gram fold, m         : sum_children n_c D^2 + p^3/3 + (D-p) p^2 + (D-p)^2 p,
-//                          D = m p + 1 (Gram-form children: D^2/2 additions)
+//   Gram fold, m, panel  : 2 K D p + 2 K Dt + 2 p^3/3 + Dt p^2 + 2 Dt p
+//   Gram fold, m, blocks : Ds (Ds + 1) (K + p)
+//                          with K the rows of the region's observation-space
+//                          children, D = m p + 1, Dt = D - p, Ds = (m-1) p
+//                          (knot-space children contribute additions only)
 static void plan_flops(const HostTree& h, Plan& t) {
     const int M = h.M;
     const double p = h.rhat;
@@ -178,6 +182,7 @@ static void plan_flops(const HostTree& h, Plan& t) {
     t.fl_pfin.assign(M, 0.0);
     t.fl_factor.assign(M, 0.0);
     t.fl_gram.assign(M, 0.0);
+    t.fl_gtile.assign(M, 0.0);
     for (int q = 0; q < 3; ++q) t.fl_fsmall[q].assign(M, 0.0);
     for (int m = 1; m < M; ++m) {
         const double nr = double(t.prior_tasks[m].size());
@@ -190,17 +195,18 @@ static void plan_flops(const HostTree& h, Plan& t) {
         for (int g : t.factor_tasks[m]) t.fl_factor[m] += ff(g);
         for (int q = 0; q < 3; ++q)
             for (int g : t.fsmall_tasks[q][m]) t.fl_fsmall[q][m] += ff(g);
-        const double D = m * p + 1;
+        const double D = m * p + 1, Dt = D - p, Ds = (m - 1) * p;
         for (int g : t.gram_tasks[m]) {
             const int64_t k = g - h.lvl_start[m - 1];
-            double f = p * p * p / 3.0 + (D - p) * p * p + (D - p) * (D - p) * p;
+            double kf = 0.0;  // rows of the observation-space children
             for (int j = 0; j < h.J; ++j) {
                 const int64_t gc = h.lvl_start[m] + h.J * k + j;
-                const double nc = double(h.obs_hi[gc] - h.obs_lo[gc]);
-                if (m + 1 == M || t.form[gc] == FOLD_FACTOR) f += nc * D * D;
-                else f += D * D / 2;
+                if (m + 1 == M || t.form[gc] == FOLD_FACTOR) kf += double(h.obs_hi[gc] - h.obs_lo[gc]);
             }
-            t.fl_gram[m] += f;
+            // panel: first block column and data row of G, factor, inverse, Z, data row of S
+            t.fl_gram[m] += 2 * kf * D * p + 2 * kf * Dt + p * p * p * (2.0 / 3.0) + Dt * p * p + 2 * Dt * p;
+            // blocks of S below the data row (lower triangle): G part and Z Z^T
+            t.fl_gtile[m] += Ds * (Ds + 1) * (kf + p);
         }
     }
     const double L = M - 1;
@@ -330,8 +336,9 @@ hipEvent_t pooled_event() {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
-const char* const KIND_NAMES[] = {"k_chain", "k_prior_finish", "k_leaf_finish", "k_fold_factor", "k_fold_gram",
-                                  "k_final", "k_small_leaf", "k_small_fold", "k_pred_leaf", "k_pred_fold"};
+const char* const KIND_NAMES[] = {"k_chain",     "k_prior_finish", "k_leaf_finish", "k_fold_factor",
+                                  "k_gram_panel", "k_final",       "k_small_leaf",  "k_small_fold",
+                                  "k_pred_leaf",  "k_pred_fold",   "k_gram_tile"};
 }  // namespace
 
 template <class F>
@@ -592,10 +599,13 @@ static hipError_t enqueue_fold(const mra_tree* t, const Plan& pl, KArgs a, int m
         return e;
     a.tasks = pl.d_gramt[m];
     a.ntasks = int64_t(pl.gram_tasks[m].size());
-    if (a.ntasks > 0 && (e = timed(4, m, pl.fl_gram[m] * nb, st, [&] {
-                             return launch_fold_gram(a, int(std::min<int64_t>(a.ntasks * nb, 1 << 16)), st);
-                         })))
-        return e;
+    if (a.ntasks > 0) {
+        if ((e = timed(4, m, pl.fl_gram[m] * nb, st, [&] {
+                 return launch_gram_panel(a, int(std::min<int64_t>(a.ntasks * nb, 1 << 16)), st);
+             })))
+            return e;
+        if (m > 1 && (e = timed(10, m, pl.fl_gtile[m] * nb, st, [&] { return launch_gram_tile(a, st); }))) return e;
+    }
     return hipSuccess;
 }
 
