@@ -401,29 +401,39 @@ struct Smem {
 // earlier levels.  A V^i in accumulator layout serves directly as the B
 // operand: the summation index is permuted consistently on the A operand,
 // which is staged in LDS one P x P block at a time.
-// Stage a P x P block (row-major, ld; rows 16-byte aligned) into LDS
+// Staging of a P x P block (row-major, ld; rows 16-byte aligned) into LDS,
 // transposed with an odd pitch: blk[c * (P + 1) + r] = src[r][c], so that the
 // 16 lanes of a group, which read 16 consecutive rows r of one column c, hit
-// 16 different banks.  All loads of a thread are issued before any store.
+// 16 different banks.  Split in two for software pipelining: the loads of the
+// next block (into registers) are issued before the current block is used, so
+// their latency overlaps the matrix-core work; the stores into LDS follow.
 template <int P>
-__device__ __forceinline__ void stage_block(double* blk, const double* src, int64_t ld) {
-    constexpr int E2 = P * P / 2;                 // double2 elements
+struct StageRegs {
+    double2 v[(P * P / 2 + NT - 1) / NT];
+};
+template <int P>
+__device__ __forceinline__ void stage_load(StageRegs<P>& rg, const double* src, int64_t ld) {
+    constexpr int E2 = P * P / 2;
     constexpr int PER = (E2 + NT - 1) / NT;
-    double2 tmp[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int e = threadIdx.x + j * NT;
         const int r = (2 * e) / P, c = (2 * e) % P;
         const bool ok = e < E2;
-        tmp[j] = *reinterpret_cast<const double2*>(src + (ok ? int64_t(r) * ld + c : 0));
+        rg.v[j] = *reinterpret_cast<const double2*>(src + (ok ? int64_t(r) * ld + c : 0));
     }
+}
+template <int P>
+__device__ __forceinline__ void stage_store(double* blk, const StageRegs<P>& rg) {
+    constexpr int E2 = P * P / 2;
+    constexpr int PER = (E2 + NT - 1) / NT;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int e = threadIdx.x + j * NT;
         if (e < E2) {
             const int r = (2 * e) / P, c = (2 * e) % P;
-            blk[c * (P + 1) + r] = tmp[j].x;
-            blk[(c + 1) * (P + 1) + r] = tmp[j].y;
+            blk[c * (P + 1) + r] = rg.v[j].x;
+            blk[(c + 1) * (P + 1) + r] = rg.v[j].y;
         }
     }
 }
@@ -435,6 +445,10 @@ __global__ void __launch_bounds__(NT) k_chain(KArgs a) {
     __shared__ double blk[P * (P + 1)];
     __shared__ double akx[MAXL * P], aky[MAXL * P];
     __shared__ int64_t voff[MAXL];
+    // the staged blocks of one row tile, in the order the loops below use them:
+    // offset into the theta's V stores and row stride
+    __shared__ int64_t soff[MAXL * (MAXL + 1) / 2];
+    __shared__ int sld[MAXL * (MAXL + 1) / 2];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
     const int64_t total = a.ntasks * a.ntheta;
     const int m = mode == 0 ? a.level : a.M - 1;  // level of the task region
@@ -449,6 +463,37 @@ __global__ void __launch_bounds__(NT) k_chain(KArgs a) {
         if (tid < L) voff[tid] = a.vst_off[ancestor(a, m, k, tid + 1)];
         for (int l = 0; l < L; ++l) region_knots(a, ancestor(a, m, k, l + 1), akx + l * P, aky + l * P);
         __syncthreads();
+        int nsteps = 0;
+        if (tid == 0) {
+            // same order as the compute loops: earlier groups, then the group's
+            // diagonal blocks each followed by its right-looking updates
+            for (int g0 = 0; g0 < L; g0 += GS) {
+                for (int i = 0; i < g0; ++i)
+                    for (int l = 0; l < GS; ++l)
+                        if (g0 + l < L) { soff[nsteps] = voff[g0 + l] + int64_t(i) * P; sld[nsteps] = (g0 + l + 1) * P; ++nsteps; }
+                for (int i = 0; i < GS; ++i) {
+                    if (g0 + i >= L) continue;
+                    const int li = g0 + i;
+                    soff[nsteps] = voff[li] + int64_t(li) * P; sld[nsteps] = (li + 1) * P; ++nsteps;
+                    for (int l = i + 1; l < GS; ++l)
+                        if (g0 + l < L) { soff[nsteps] = voff[g0 + l] + int64_t(li) * P; sld[nsteps] = (g0 + l + 1) * P; ++nsteps; }
+                }
+            }
+        }
+        nsteps = L * (L + 1) / 2;
+        __syncthreads();
+        StageRegs<P> pf;
+        if (nsteps > 0) stage_load<P>(pf, vst + soff[0], sld[0]);
+        int step = 0;
+        // stage block `step` (held in pf) into LDS and start loading the next
+        auto advance = [&]() {
+            __syncthreads();
+            stage_store<P>(blk, pf);
+            __syncthreads();
+            const int nx = (step + 1 < nsteps) ? step + 1 : 0;
+            stage_load<P>(pf, vst + soff[nx], sld[nx]);
+            ++step;
+        };
         int nrows;
         int64_t lo = 0, ldd;
         double* dst;
@@ -463,6 +508,7 @@ __global__ void __launch_bounds__(NT) k_chain(KArgs a) {
             dst = a.F + th * a.F_stride + lo * a.WFs;
         }
         for (int r0 = 0; r0 < nrows; r0 += 64) {
+            step = 0;
             const int rr = r0 + 16 * w + lr;
             const bool valid = rr < nrows && (mode == 1 || rr < a.rhat);
             const bool store = mode == 0 ? (rr < P) : (rr < nrows);
@@ -500,9 +546,7 @@ __global__ void __launch_bounds__(NT) k_chain(KArgs a) {
 #pragma unroll
                     for (int l = 0; l < GS; ++l) {
                         if (g0 + l < L) {
-                            __syncthreads();
-                            stage_block<P>(blk, vst + voff[g0 + l] + int64_t(i) * P, int64_t(g0 + l + 1) * P);
-                            __syncthreads();
+                            advance();
 #pragma unroll
                             for (int mt2 = 0; mt2 < NM; ++mt2)
 #pragma unroll
@@ -520,9 +564,7 @@ __global__ void __launch_bounds__(NT) k_chain(KArgs a) {
                 for (int i = 0; i < GS; ++i) {
                     if (g0 + i < L) {
                         const int li = g0 + i;
-                        __syncthreads();
-                        stage_block<P>(blk, vst + voff[li] + int64_t(li) * P, int64_t(li + 1) * P);
-                        __syncthreads();
+                        advance();
                         v4d vi[NM];
 #pragma unroll
                         for (int mt = 0; mt < NM; ++mt) {
@@ -544,9 +586,7 @@ __global__ void __launch_bounds__(NT) k_chain(KArgs a) {
 #pragma unroll
                         for (int l = i + 1; l < GS; ++l) {
                             if (g0 + l < L) {
-                                __syncthreads();
-                                stage_block<P>(blk, vst + voff[g0 + l] + int64_t(li) * P, int64_t(g0 + l + 1) * P);
-                                __syncthreads();
+                                advance();
 #pragma unroll
                                 for (int mt2 = 0; mt2 < NM; ++mt2)
 #pragma unroll
