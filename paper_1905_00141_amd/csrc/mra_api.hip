@@ -259,8 +259,10 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
                 if (np <= 16 && np <= smax) t.fsmall_tasks[0][m].push_back(int(g));
                 else if (np <= 32 && np <= smax) t.fsmall_tasks[1][m].push_back(int(g));
                 else if (np <= 64 && np <= smax) t.fsmall_tasks[2][m].push_back(int(g));
-                else t.factor_tasks[m].push_back(int(g));
-                if (np > 64) t.scratch_fold = std::max(t.scratch_fold, np * np);
+                else {
+                    t.factor_tasks[m].push_back(int(g));
+                    t.scratch_fold = std::max(t.scratch_fold, np * np);
+                }
             } else {
                 t.form[g] = FOLD_GRAM;
                 t.gram_tasks[m].push_back(int(g));
@@ -279,7 +281,7 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
         const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
         if (nc > smax) {
             t.leaf_tasks.push_back(int(g));
-            if (nc > 64) t.scratch_leaf = std::max(t.scratch_leaf, nc * nc);
+            t.scratch_leaf = std::max(t.scratch_leaf, nc * nc);
         } else if (nc > 32) {
             t.small_tasks[2].push_back(int(g));
         } else if (nc > 16) {

@@ -381,7 +381,7 @@ __device__ __forceinline__ void wg_trsm_lln(const double* L, int64_t ldl, int n,
 // ------------------------------------------------------------------ kernels
 
 struct Smem {
-    double mm[2 * MK * MLD];
+    double mm[NT];  // reduction scratch (wg_rowvec)
     double L[TB * MLD];
     double Li[TB * MLD];
     double kx[TB], ky[TB];
@@ -394,7 +394,7 @@ struct Smem {
 // level-(M-1) region for ancestors 1..M-1, written into the F buffer (block of
 // level l at columns (M-1-l)P).  For ancestor level l, with C the covariance:
 //     V^l = ( C(rows, Q_{A_l}) - sum_{i<l} V^i V^i(Q_{A_l})^T ) L_{A_l}^{-T}.
-// Each wave owns 16 rows.  Ancestor levels are taken in groups of GS = 256/P:
+// Each wave owns 16 rows.  Ancestor levels are taken in groups of GS = 128/P:
 // one pending accumulator per level of the group (MFMA destinations, knots x
 // rows) receives the covariance, the contributions of all earlier groups (their
 // V rows read back from memory) and, right-looking, those of the group's own
@@ -439,9 +439,9 @@ __device__ __forceinline__ void stage_store(double* blk, const StageRegs<P>& rg)
 }
 
 template <int P, int mode>
-__global__ void __launch_bounds__(NT) k_chain(KArgs a) {
+__global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
     constexpr int NM = P / 16;
-    constexpr int GS = 256 / P;
+    constexpr int GS = 128 / P;  // accumulator budget for two workgroups per CU
     __shared__ double blk[P * (P + 1)];
     __shared__ double akx[MAXL * P], aky[MAXL * P];
     __shared__ int64_t voff[MAXL];
@@ -689,7 +689,7 @@ __global__ void __launch_bounds__(NT) k_prior_finish_w(KArgs a) {
 enum { FIN_LEAF = 0, FIN_FOLD = 1 };
 
 template <int NMAX, int MODE>
-__global__ void __launch_bounds__(NT) k_small(KArgs a) {
+__global__ void __launch_bounds__(NT, (NMAX <= 32 ? 2 : 1)) k_small(KArgs a) {
     constexpr int LDT = NMAX + 1;
     constexpr int NR = NMAX / 16;
     __shared__ double T[4][NMAX * LDT];
@@ -799,10 +799,9 @@ __global__ void __launch_bounds__(NT) k_small(KArgs a) {
 
 // Finest-level regions: S = C(S,S) - sum_l V^l V^l^T + tau I, its Cholesky
 // factor, d = log det S, and F <- L_S^{-1} [V^{M-1} .. V^1 | z] in place.
-// Leaves of up to 64 observations keep S in LDS.
+// S lives in the workgroup's global scratch slot (n^2 doubles).
 __global__ void __launch_bounds__(NT) k_leaf_finish(KArgs a) {
     __shared__ Smem s;
-    __shared__ double Sl[TB * MLD];
     const int64_t total = a.ntasks * a.ntheta;
     const int M = a.M;
     double* Sg = a.scratch + blockIdx.x * a.scratch_stride;
@@ -816,8 +815,8 @@ __global__ void __launch_bounds__(NT) k_leaf_finish(KArgs a) {
         double* Frows = a.F + th * a.F_stride + lo * a.WFs;
         const double* px = a.x + lo;
         const double* py = a.y + lo;
-        double* S = (n <= TB) ? Sl : Sg;
-        const int64_t lds = (n <= TB) ? MLD : n;
+        double* S = Sg;
+        const int64_t lds = n;
         for (int r = threadIdx.x; r < n; r += NT) Frows[int64_t(r) * a.WFs + (a.WF - 1)] = a.z[lo + r];
         for (int64_t e0 = 0; e0 < int64_t(n) * n; e0 += 4 * NT) {
             double xi[4], yi[4], xj[4], yj[4];
@@ -854,9 +853,8 @@ __global__ void __launch_bounds__(NT) k_leaf_finish(KArgs a) {
 // Fold in observation space for regions at `level` whose subtree holds few
 // observations: G = I + F_m F_m^T over the region's rows (F_m: the columns of
 // this region's own knots), d = log det G, and F_rest <- L_G^{-1} F_rest.
-__global__ void __launch_bounds__(NT) k_fold_factor(KArgs a) {
+__global__ void __launch_bounds__(NT, 2) k_fold_factor(KArgs a) {
     __shared__ Smem s;
-    __shared__ double Gl[TB * MLD];
     const int64_t total = a.ntasks * a.ntheta;
     const int m = a.level, P = a.P;
     const int cm = (a.M - 1 - m) * P;
@@ -867,8 +865,8 @@ __global__ void __launch_bounds__(NT) k_fold_factor(KArgs a) {
         const int64_t lo = a.obs_lo[g];
         const int n = int(a.obs_hi[g] - lo);
         double* Frows = a.F + th * a.F_stride + lo * a.WFs;
-        double* G = (n <= TB) ? Gl : Gg;
-        const int64_t ldg = (n <= TB) ? MLD : n;
+        double* G = Gg;
+        const int64_t ldg = n;
         for (int64_t e = threadIdx.x; e < int64_t(n) * n; e += NT) {
             const int i = int(e / n), j = int(e % n);
             if (j <= i) G[i * ldg + j] = (i == j) ? 1.0 : 0.0;
@@ -940,7 +938,7 @@ __device__ __forceinline__ void wg_rowvec(double* y, int N, int K, const double*
     }
 }
 
-__global__ void __launch_bounds__(NT) k_gram_panel(KArgs a) {
+__global__ void __launch_bounds__(NT, 2) k_gram_panel(KArgs a) {
     __shared__ Smem s;
     const int64_t total = a.ntasks * a.ntheta;
     const int m = a.level, P = a.P, M = a.M;
