@@ -111,6 +111,32 @@ def measured_traffic(name, level):
     return None
 
 
+def bench_predict(mra, synth, torch, dev, reps=3):
+    """Kriging throughput at 16384 held-out points of the n = 131072, M = 7,
+    r = 64 Matern-3/2 workload (device-resident inputs), and its accuracy
+    against the field the data were drawn from."""
+    import numpy as np
+    c = synth.config2(device="cuda")
+    t = mra.Tree(c["x"], c["y"], c["z"], J=c["J"], r=c["r"], M=c["M"], domain=c["domain"])
+    th = c["theta"][0]
+    px = torch.tensor(c["px"], dtype=torch.float64, device=dev)
+    py = torch.tensor(c["py"], dtype=torch.float64, device=dev)
+    m, v = t.predict(th, px, py, "matern", 1.5)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        m, v = t.predict(th, px, py, "matern", 1.5)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    m, v = m.cpu().numpy(), v.cpu().numpy()
+    err = m - c["truth"]
+    cover = float(np.mean(np.abs(err) <= 1.96 * np.sqrt(v)))
+    log(f"[bench] kriging: {len(px)} points in {1000 * sec:.1f} ms, MSPE {np.mean(err ** 2):.4e}")
+    return {"workload": f"{c['name']}_pred{len(px)}", "ms": 1000 * sec, "points_per_s": len(px) / sec,
+            "mspe": float(np.mean(err ** 2)), "field_var": float(np.var(c["truth"])),
+            "coverage_95": cover}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +151,8 @@ def main():
     ap.add_argument("--mle", action="store_true",
                     help="also run the MLE searches on the same tree (32x32 profiled grid, Nelder-Mead without and "
                          "with the surrogate trained on 2048 exact evaluations) and report exact-evaluation counts")
+    ap.add_argument("--predict", action="store_true",
+                    help="also time kriging on the n = 131072, M = 7 uniform workload at its 16384 held-out points")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the run, launch a fill and a plain FP64 copy kernel of MIB MiB each: the "
                          "reference that scales hardware byte counters (FETCH_SIZE, WRITE_SIZE)")
@@ -247,6 +275,8 @@ def main():
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: fill and copy of {args.copy_calibration} MiB")
+    if args.predict:
+        res["predict"] = bench_predict(mra, synth, torch, dev)
     if args.mle:
         from paper_1905_00141_amd import mle
         t0 = time.time()
