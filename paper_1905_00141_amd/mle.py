@@ -17,7 +17,8 @@ Three searches, each counting exact evaluations:
   * local: a derivative-free Nelder-Mead search on exact values from the
     centre of the box (the method without the surrogate);
   * surrogate: the network (include/mra_mlp.h) is trained on exact
-    log-likelihoods at Sobol points of the (log alpha, log beta, log tau) box,
+    log-likelihoods (monotonically compressed near their maximum) at Sobol
+    points of the (log alpha, log beta, log tau) box,
     its maximum over a dense grid is the proposal, and the same Nelder-Mead
     search on exact values starts there with a smaller simplex.
 The exact MRA stays the judge of every reported value.
@@ -35,6 +36,9 @@ import numpy as np
 from . import mra, synth
 
 LOG2PI = math.log(2.0 * math.pi)
+
+# scale (nats) of the compression of the surrogate's training targets
+TARGET_SCALE = 10.0
 
 # search box of the profiled problem: range and nugget-to-sill ratio
 BETA_LO, BETA_HI = 0.02, 0.3
@@ -175,8 +179,14 @@ def train_surrogate(tree: mra.Tree, n_train=2048, seed=5, steps=3000, lr=3e-3, f
         if log:
             log(f"[mle] surrogate training set: {min(s + 64, n_train)} of {n_train} exact evaluations")
     t_exact = time.time() - t0
+    # The log-likelihood spans many orders of nats over the box; the network
+    # is fitted to a monotone compression of it, -log(1 + (max - y) / s),
+    # which keeps its maximiser and resolves the region near the best
+    # training value (s = 10 nats) instead of the far tails.
+    yt = -np.log1p((y.max() - y) / TARGET_SCALE)
     net = mra.Mlp(synth.mlp_init(seed))
-    net.set_scaling(lo, hi, float(y.mean()), float(y.std()))
+    net.set_scaling(lo, hi, float(yt.mean()), float(yt.std()))
+    y = yt
     xf = X.astype(np.float32)
     t0 = time.time()
     loss = None
