@@ -261,7 +261,8 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
                 else if (np <= 64 && np <= smax) t.fsmall_tasks[2][m].push_back(int(g));
                 else {
                     t.factor_tasks[m].push_back(int(g));
-                    t.scratch_fold = std::max(t.scratch_fold, np * np);
+                    // the matrix and the inverses of its 64 x 64 diagonal blocks
+                    t.scratch_fold = std::max(t.scratch_fold, np * np + ((np + 63) / 64) * 4096);
                 }
             } else {
                 t.form[g] = FOLD_GRAM;
@@ -281,7 +282,7 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
         const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
         if (nc > smax) {
             t.leaf_tasks.push_back(int(g));
-            t.scratch_leaf = std::max(t.scratch_leaf, nc * nc);
+            t.scratch_leaf = std::max(t.scratch_leaf, nc * nc + ((nc + 63) / 64) * 4096);
         } else if (nc > 32) {
             t.small_tasks[2].push_back(int(g));
         } else if (nc > 16) {

@@ -328,13 +328,16 @@ __device__ __forceinline__ void store_tile(double* G, int64_t ldg, const double*
 // as products with the inverted block.  *logdet (all threads) = sum log diag.
 // For n <= 64, Li holds L^{-1} on return.
 __device__ __forceinline__ bool wg_potrf(double* A, int64_t lda, int n, double* Ls, double* Li, double* sm,
-                                         int* flag, double* logdet) {
+                                         int* flag, double* logdet, double* Lst = nullptr) {
     double acc = 0.0;
     for (int j0 = 0; j0 < n; j0 += TB) {
         const int jb = min(TB, n - j0);
         double* Ajj = A + int64_t(j0) * lda + j0;
         load_tile(Ls, MLD, Ajj, lda, jb);
         if (wg_potrf_inv_lds(Ls, jb, MLD, Li, MLD, flag)) return true;
+        // keep the block's inverse for a later triangular solve
+        if (Lst)
+            for (int e = threadIdx.x; e < TB * TB; e += NT) Lst[int64_t(j0 / TB) * TB * TB + e] = Li[(e / TB) * MLD + (e % TB)];
         store_tile(Ajj, lda, Ls, MLD, jb);
         for (int i = 0; i < jb; ++i) acc += log(Ls[i * MLD + i]);
         const int rest = n - j0 - jb;
@@ -355,10 +358,15 @@ __device__ __forceinline__ bool wg_potrf(double* A, int64_t lda, int n, double* 
 // Diagonal blocks are inverted in LDS and applied as products; with n <= 64
 // and have_inv the inverse already in Li is used.
 __device__ __forceinline__ void wg_trsm_lln(const double* L, int64_t ldl, int n, double* X, int64_t ldx, int W,
-                                            double* Ls, double* Li, double* sm, int* flag, bool have_inv) {
+                                            double* Ls, double* Li, double* sm, int* flag, bool have_inv,
+                                            const double* Lst = nullptr) {
     for (int i0 = 0; i0 < n; i0 += TB) {
         const int ib = min(TB, n - i0);
-        if (!(have_inv && n <= TB)) {
+        if (Lst && n > TB) {
+            // the diagonal blocks' inverses kept by wg_potrf
+            for (int e = threadIdx.x; e < TB * TB; e += NT) Li[(e / TB) * MLD + (e % TB)] = Lst[int64_t(i0 / TB) * TB * TB + e];
+            __syncthreads();
+        } else if (!(have_inv && n <= TB)) {
             load_tile(Ls, MLD, L + int64_t(i0) * ldl + i0, ldl, ib);
             // the block is already a factor: its Cholesky factor is itself up to
             // rounding of the diagonal; take the inverse of the stored factor
@@ -841,12 +849,13 @@ __global__ void __launch_bounds__(NT) k_leaf_finish(KArgs a) {
         __syncthreads();
         if (M > 1) wg_mm<MM_SUB>(S, lds, n, n, (M - 1) * a.P, Frows, a.WFs, 1, Frows, a.WFs, 1, true, s.mm);
         double logdet = 0.0;
-        if (wg_potrf(S, lds, n, s.L, s.Li, s.mm, &s.flag, &logdet)) {
+        double* Lst = S + int64_t(n) * n;  // inverses of the diagonal blocks
+        if (wg_potrf(S, lds, n, s.L, s.Li, s.mm, &s.flag, &logdet, Lst)) {
             flag_fail(a, th, g);
             continue;
         }
         if (threadIdx.x == 0) a.dval[th * a.d_stride + g] = 2.0 * logdet;
-        wg_trsm_lln(S, lds, n, Frows, a.WFs, a.WF, s.L, s.Li, s.mm, &s.flag, true);
+        wg_trsm_lln(S, lds, n, Frows, a.WFs, a.WF, s.L, s.Li, s.mm, &s.flag, true, Lst);
     }
 }
 
@@ -874,12 +883,13 @@ __global__ void __launch_bounds__(NT, 2) k_fold_factor(KArgs a) {
         __syncthreads();
         wg_mm<MM_ADD>(G, ldg, n, n, P, Frows + cm, a.WFs, 1, Frows + cm, a.WFs, 1, true, s.mm);
         double logdet = 0.0;
-        if (wg_potrf(G, ldg, n, s.L, s.Li, s.mm, &s.flag, &logdet)) {
+        double* Lst = G + int64_t(n) * n;  // inverses of the diagonal blocks
+        if (wg_potrf(G, ldg, n, s.L, s.Li, s.mm, &s.flag, &logdet, Lst)) {
             flag_fail(a, th, g);
             continue;
         }
         if (threadIdx.x == 0) a.dval[th * a.d_stride + g] = 2.0 * logdet;
-        wg_trsm_lln(G, ldg, n, Frows + cm + P, a.WFs, a.WF - cm - P, s.L, s.Li, s.mm, &s.flag, true);
+        wg_trsm_lln(G, ldg, n, Frows + cm + P, a.WFs, a.WF - cm - P, s.L, s.Li, s.mm, &s.flag, true, Lst);
     }
 }
 
