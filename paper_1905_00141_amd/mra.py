@@ -101,6 +101,15 @@ def load_library(path: str = LIB_PATH):
     return L
 
 
+# PyTorch (device memory and streams for the callers) carries its own HIP
+# runtime.  Loading it before this library's runtime keeps the process working
+# whichever of the two initialises the GPU first; with the opposite load order
+# this library's runtime can find no device once PyTorch has initialised it.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the library itself does not need it
+    pass
+
 _lib = load_library()
 
 
