@@ -1168,6 +1168,167 @@ __global__ void __launch_bounds__(NT, 2) k_gram_tile(KArgs a) {
     }
 }
 
+// The same blocks of S, one workgroup per 128 x 128 super-block (bi >= bj):
+// the observation-space rows are staged through LDS 16 at a time, each wave
+// computing one 64 x 64 quarter from the shared copy, so every F row segment
+// is read from memory once per super-block instead of once per 64 x 64 block.
+// The next chunk is loaded into registers while the current one is used.
+constexpr int SB = 128;       // super-block edge
+constexpr int KCH = 16;       // rows per staged chunk
+constexpr int SPAD = SB + 8;  // LDS pitch: the four 16-lane groups of a read fall on different banks
+
+__global__ void __launch_bounds__(NT, 2) k_gram_tile2(KArgs a) {
+    __shared__ double As[KCH * SPAD];
+    __shared__ double Bs[KCH * SPAD];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const int m = a.level, P = a.P, M = a.M;
+    const int cm = (M - 1 - m) * P;
+    const int D = m * P + 1, Ds = (m - 1) * P;
+    const int nsb = (Ds + SB - 1) / SB;
+    const int64_t nst = int64_t(nsb) * (nsb + 1) / 2;
+    const int64_t total = a.ntasks * a.ntheta * nst;
+    const int wr = w >> 1, wc = w & 1;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const int64_t rt = t / nst;
+        int64_t tix = t % nst;
+        int BI = 0;
+        while (tix > BI) { tix -= BI + 1; ++BI; }
+        const int BJ = int(tix);
+        const int th = int(rt / a.ntasks);
+        const int64_t g = a.tasks[rt % a.ntasks];
+        const int64_t k = g - a.lvl[m - 1];
+        double* G = a.gram + th * a.gram_stride + a.gram_off[g];
+        const double* Fth = a.F + th * a.F_stride;
+        const int R0 = BI * SB, C0 = BJ * SB;
+        const int r0 = R0 + 64 * wr, c0 = C0 + 64 * wc;  // this wave's quarter (within S)
+        const bool active = !(BI == BJ && wc > wr);      // quarters above the diagonal are skipped
+        const bool diagq = (BI == BJ && wc == wr);
+        v4d acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < a.J;) {
+            const int64_t gc = a.lvl[m] + a.J * k + j;
+            if (!child_is_rows(a, m, gc)) { ++j; continue; }
+            int j2 = j + 1;
+            while (j2 < a.J && child_is_rows(a, m, a.lvl[m] + a.J * k + j2)) ++j2;
+            const int64_t lo = a.obs_lo[gc], hi = a.obs_hi[a.lvl[m] + a.J * k + j2 - 1];
+            j = j2;
+            const int nc = int(hi - lo);
+            if (nc == 0) continue;
+            const double* base = Fth + lo * a.WFs + cm + P;  // S column x is base[x]
+            // chunk staging: 16 rows x 128 columns per operand, 4 double2 per thread each
+            double2 pa[4], pb[4];
+            auto load_chunk = [&](int k0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int idx = threadIdx.x + NT * q;
+                    const int kr = idx >> 6, c2 = (idx & 63) * 2;
+                    const bool kok = k0 + kr < nc;
+                    const bool aok = kok && R0 + c2 < Ds, bok = kok && C0 + c2 < Ds;
+                    const double* pra = base + int64_t(k0 + kr) * a.WFs + R0 + c2;
+                    const double* prb = base + int64_t(k0 + kr) * a.WFs + C0 + c2;
+                    const double2 va = *reinterpret_cast<const double2*>(aok ? pra : base);
+                    const double2 vb = *reinterpret_cast<const double2*>(bok ? prb : base);
+                    pa[q] = aok ? va : double2{0.0, 0.0};
+                    pb[q] = bok ? vb : double2{0.0, 0.0};
+                }
+            };
+            load_chunk(0);
+            for (int k0 = 0; k0 < nc; k0 += KCH) {
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int idx = threadIdx.x + NT * q;
+                    const int kr = idx >> 6, c2 = (idx & 63) * 2;
+                    *reinterpret_cast<double2*>(As + kr * SPAD + c2) = pa[q];
+                    *reinterpret_cast<double2*>(Bs + kr * SPAD + c2) = pb[q];
+                }
+                __syncthreads();
+                if (k0 + KCH < nc) load_chunk(k0 + KCH);
+                if (active) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int kk = 4 * q + lg;
+                        double fa[4], fb[4];
+#pragma unroll
+                        for (int tt = 0; tt < 4; ++tt) {
+                            fa[tt] = As[kk * SPAD + 64 * wr + 16 * tt + lr];
+                            fb[tt] = Bs[kk * SPAD + 64 * wc + 16 * tt + lr];
+                        }
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int jj = 0; jj < 4; ++jj)
+                                if (!diagq || jj <= i) acc[i][jj] = mfma(fa[i], fb[jj], acc[i][jj]);
+                    }
+                }
+            }
+        }
+        if (active) {
+            bool rv[4], cv[4];
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+                rv[tt] = r0 + 16 * tt + lr < Ds;
+                cv[tt] = c0 + 16 * tt + lr < Ds;
+            }
+            // - Z Z^T over the P columns of Z (row P + x of G holds Z row x)
+            const double* Za = G + int64_t(P + r0) * D;
+            const double* Zb = G + int64_t(P + c0) * D;
+            for (int k0 = 0; k0 < P; k0 += 16) {
+                double fa[4][4], fb[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kk = k0 + 4 * q + lg;
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt) {
+                        fa[tt][q] = ldg0(Za, int64_t(16 * tt + lr) * D + kk, rv[tt]);
+                        fb[tt][q] = ldg0(Zb, int64_t(16 * tt + lr) * D + kk, cv[tt]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj)
+                            if (!diagq || jj <= i) acc[i][jj] = mfma(-fa[i][q], fb[jj][q], acc[i][jj]);
+            }
+            // the lower part of the quarter, written once, knot-space children added
+            const int Dc = D + P;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                double add[4][4];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) add[jj][e] = 0.0;
+                for (int j = 0; j < a.J; ++j) {
+                    const int64_t gc = a.lvl[m] + a.J * k + j;
+                    if (child_is_rows(a, m, gc)) continue;
+                    const double* Gc = a.gram + th * a.gram_stride + a.gram_off[gc];
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int r = r0 + 16 * i + lg + 4 * e, c = c0 + 16 * jj + lr;
+                            add[jj][e] += ldg0(Gc, int64_t(2 * P + r) * Dc + 2 * P + c, r < Ds && c < Ds && c <= r);
+                        }
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = r0 + 16 * i + lg + 4 * e, c = c0 + 16 * jj + lr;
+                        if (r < Ds && c < Ds && c <= r) G[int64_t(P + r) * D + P + c] = acc[i][jj][e] + add[jj][e];
+                    }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------- prediction
 // Kriging of the latent process at prediction points (one theta).  A point p
 // joins the finest-level set of its leaf R; with V(p) its whitened prior rows,
@@ -1404,6 +1565,14 @@ hipError_t launch_fold_factor(const KArgs& a, int grid, hipStream_t st) {
 }
 hipError_t launch_gram_panel(const KArgs& a, int grid, hipStream_t st) {
     hipLaunchKernelGGL(k_gram_panel, dim3(grid), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_gram_tile2(const KArgs& a, hipStream_t st) {
+    const int Ds = (a.level - 1) * a.P;
+    const int64_t nsb = (Ds + SB - 1) / SB;
+    const int64_t blocks = std::min<int64_t>(a.ntasks * a.ntheta * nsb * (nsb + 1) / 2, int64_t(1) << 20);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gram_tile2, dim3(unsigned(blocks)), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 hipError_t launch_gram_tile(const KArgs& a, hipStream_t st) {
