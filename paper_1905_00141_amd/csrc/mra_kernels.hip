@@ -450,8 +450,12 @@ template <int P, int mode>
 __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
     constexpr int NM = P / 16;
     constexpr int GS = 128 / P;  // accumulator budget for two workgroups per CU
-    __shared__ double blk[P * (P + 1)];
-    __shared__ double akx[MAXL * P], aky[MAXL * P];
+    // two staging buffers: block s is written while block s - 1 may still be
+    // read, so one barrier per block suffices
+    __shared__ double blk2[2][P * (P + 1)];
+    // the ancestors' knot bars (a knot is a pair of bars, r_hat <= 64 gives <= 8 each)
+    __shared__ double kbx[MAXL * 8], kby[MAXL * 8];
+    __shared__ int kq[P];  // knot q -> its bars: (q % nx) + 8 (q / nx), or -1 beyond r_hat
     __shared__ int64_t voff[MAXL];
     // the staged blocks of one row tile, in the order the loops below use them:
     // offset into the theta's V stores and row stride
@@ -461,6 +465,8 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
     const int64_t total = a.ntasks * a.ntheta;
     const int m = mode == 0 ? a.level : a.M - 1;  // level of the task region
     const int L = mode == 0 ? m - 1 : a.M - 1;    // ancestor levels of the rows
+    int ph = 0;  // staging buffer parity, continued across tiles and tasks
+    for (int q = threadIdx.x; q < P; q += NT) kq[q] = q < a.rhat ? (q % a.nx) + 8 * (q / a.nx) : -1;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         const int th = int(t / a.ntasks);
         const int64_t g = a.tasks[t % a.ntasks];
@@ -469,7 +475,12 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
         const double alpha = thp[0], inv_beta = 1.0 / thp[1];
         const double* vst = a.vst + th * a.vst_stride;
         if (tid < L) voff[tid] = a.vst_off[ancestor(a, m, k, tid + 1)];
-        for (int l = 0; l < L; ++l) region_knots(a, ancestor(a, m, k, l + 1), akx + l * P, aky + l * P);
+        if (tid < 8 * L) {
+            const int l = tid >> 3, pb = tid & 7;
+            const double* bx = a.box + 4 * ancestor(a, m, k, l + 1);
+            kbx[tid] = pb < a.nx ? grid_bar(bx[0], bx[1], a.nx, a.offset, pb) : 0.0;
+            kby[tid] = pb < a.ny ? grid_bar(bx[2], bx[3], a.ny, a.offset, pb) : 0.0;
+        }
         __syncthreads();
         int nsteps = 0;
         if (tid == 0) {
@@ -493,14 +504,17 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
         StageRegs<P> pf;
         if (nsteps > 0) stage_load<P>(pf, vst + soff[0], sld[0]);
         int step = 0;
-        // stage block `step` (held in pf) into LDS and start loading the next
-        auto advance = [&]() {
-            __syncthreads();
+        // stage block `step` (held in pf) into the next LDS buffer, start
+        // loading the one after, and return the staged copy
+        auto advance = [&]() -> const double* {
+            double* blk = blk2[ph & 1];
+            ++ph;
             stage_store<P>(blk, pf);
             __syncthreads();
             const int nx = (step + 1 < nsteps) ? step + 1 : 0;
             stage_load<P>(pf, vst + soff[nx], sld[nx]);
             ++step;
+            return blk;
         };
         int nrows;
         int64_t lo = 0, ldd;
@@ -537,9 +551,11 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
                         for (int i = 0; i < 4; ++i) {
                             const int q = 16 * mt + lg + 4 * i;
                             const int la = g0 + l;
-                            acc[l][mt][i] = (la < L && valid && q < a.rhat)
-                                                ? cov_pts(akx[la * P + q], aky[la * P + q], px, py, alpha, inv_beta, a.smooth)
-                                                : 0.0;
+                            const int kk = kq[q];
+                            const bool ok = la < L && valid && kk >= 0;
+                            acc[l][mt][i] = ok ? cov_pts(kbx[la * 8 + (kk & 7)], kby[la * 8 + (kk >> 3)], px, py, alpha,
+                                                         inv_beta, a.smooth)
+                                               : 0.0;
                         }
                 // earlier groups: acc_l -= V^{i+1}(Q_{A_l}) V^{i+1}
                 for (int i = 0; i < g0; ++i) {
@@ -554,7 +570,7 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
 #pragma unroll
                     for (int l = 0; l < GS; ++l) {
                         if (g0 + l < L) {
-                            advance();
+                            const double* blk = advance();
 #pragma unroll
                             for (int mt2 = 0; mt2 < NM; ++mt2)
 #pragma unroll
@@ -572,7 +588,7 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
                 for (int i = 0; i < GS; ++i) {
                     if (g0 + i < L) {
                         const int li = g0 + i;
-                        advance();
+                        const double* blk = advance();
                         v4d vi[NM];
 #pragma unroll
                         for (int mt = 0; mt < NM; ++mt) {
@@ -594,7 +610,7 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
 #pragma unroll
                         for (int l = i + 1; l < GS; ++l) {
                             if (g0 + l < L) {
-                                advance();
+                                const double* blk = advance();
 #pragma unroll
                                 for (int mt2 = 0; mt2 < NM; ++mt2)
 #pragma unroll
