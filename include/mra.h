@@ -59,7 +59,7 @@ typedef struct mra_tree mra_tree;
  *   J       : 2 (split the longer side, x on a tie) or 4 (halve both sides).
  *   r       : requested knots per region above the finest level; the knots
  *             form a ceil(sqrt r) x floor(r / ceil(sqrt r)) grid, so
- *             r_hat = that product knots are placed.  This build supports
+ *             r_hat = that product knots are placed.  The library supports
  *             r_hat <= 64 (MRA_EINVAL beyond).
  *   M       : number of levels, >= 1.  The finest level holds the observations
  *             as its knots.

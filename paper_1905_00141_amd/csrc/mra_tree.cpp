@@ -67,7 +67,7 @@ int build_host_tree(const double* x, const double* y, const double* z, int64_t n
     const int ny = r / nx;
     t.J = J; t.M = M; t.r = r; t.nx = nx; t.ny = ny; t.rhat = nx * ny;
     if (t.rhat > 64) {
-        err = "r_hat > 64 is not supported by this build";
+        err = "r_hat > 64 is not supported (the kernel tiles hold at most 64 knots)";
         return MRA_EINVAL;
     }
     t.P = t.rhat <= 16 ? 16 : (t.rhat <= 32 ? 32 : 64);
