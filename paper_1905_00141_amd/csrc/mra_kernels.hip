@@ -533,6 +533,10 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
             step = 0;
             const int rr = r0 + 16 * w + lr;
             const bool valid = rr < nrows && (mode == 1 || rr < a.rhat);
+            // a wave whose 16 rows all lie past the region's last observation
+            // (the ragged last tile) still stages blocks and meets every
+            // barrier, but leaves the matrix core to the other workgroup
+            const bool act = mode == 0 || __builtin_amdgcn_readfirstlane(r0 + 16 * w) < nrows;
             const bool store = mode == 0 ? (rr < P) : (rr < nrows);
             double px = 0.0, py = 0.0;
             if (valid) {
@@ -571,6 +575,7 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
                     for (int l = 0; l < GS; ++l) {
                         if (g0 + l < L) {
                             const double* blk = advance();
+                            if (!act) continue;
 #pragma unroll
                             for (int mt2 = 0; mt2 < NM; ++mt2)
 #pragma unroll
@@ -590,27 +595,30 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
                         const int li = g0 + i;
                         const double* blk = advance();
                         v4d vi[NM];
+                        if (act) {
 #pragma unroll
-                        for (int mt = 0; mt < NM; ++mt) {
-                            v4d vn = v4d{0.0, 0.0, 0.0, 0.0};
+                            for (int mt = 0; mt < NM; ++mt) {
+                                v4d vn = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                            for (int mt2 = 0; mt2 <= mt; ++mt2)
+                                for (int mt2 = 0; mt2 <= mt; ++mt2)
 #pragma unroll
-                                for (int q = 0; q < 4; ++q)
-                                    vn = mfma(blk[(16 * mt2 + lg + 4 * q) * (P + 1) + 16 * mt + lr], acc[i][mt2][q], vn);
-                            vi[mt] = vn;
-                        }
-                        if (store) {
-                            double* d = drow + colof(li);
+                                    for (int q = 0; q < 4; ++q)
+                                        vn = mfma(blk[(16 * mt2 + lg + 4 * q) * (P + 1) + 16 * mt + lr], acc[i][mt2][q], vn);
+                                vi[mt] = vn;
+                            }
+                            if (store) {
+                                double* d = drow + colof(li);
 #pragma unroll
-                            for (int mt = 0; mt < NM; ++mt)
+                                for (int mt = 0; mt < NM; ++mt)
 #pragma unroll
-                                for (int q = 0; q < 4; ++q) d[16 * mt + lg + 4 * q] = vi[mt][q];
+                                    for (int q = 0; q < 4; ++q) d[16 * mt + lg + 4 * q] = vi[mt][q];
+                            }
                         }
 #pragma unroll
                         for (int l = i + 1; l < GS; ++l) {
                             if (g0 + l < L) {
                                 const double* blk = advance();
+                                if (!act) continue;
 #pragma unroll
                                 for (int mt2 = 0; mt2 < NM; ++mt2)
 #pragma unroll
