@@ -745,22 +745,30 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 2 : 1)) k_small(KArgs a) {
         v4d acc[NR * (NR + 1) / 2];
 #pragma unroll
         for (int e = 0; e < NR * (NR + 1) / 2; ++e) acc[e] = v4d{0.0, 0.0, 0.0, 0.0};
-        for (int kb = 0; kb < K; kb += 16) {
-            v4d fr[NR];
+        // KD k-steps of 16 per batch: their loads are issued together (K is a
+        // multiple of 16)
+        constexpr int KD = NR <= 2 ? 4 : 2;
+        for (int kb = 0; kb < K; kb += 16 * KD) {
+            v4d fr[KD][NR];
 #pragma unroll
-            for (int rt = 0; rt < NR; ++rt) {
-                const int row = 16 * rt + lr;
-                fr[rt] = v4d{0.0, 0.0, 0.0, 0.0};
-                if (row < n) fr[rt] = *reinterpret_cast<const v4d*>(Fr + int64_t(row) * a.WFs + kc0 + kb + 4 * lg);
-            }
+            for (int d = 0; d < KD; ++d)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                int e = 0;
+                for (int rt = 0; rt < NR; ++rt) {
+                    const int row = 16 * rt + lr;
+                    fr[d][rt] = v4d{0.0, 0.0, 0.0, 0.0};
+                    if (row < n && kb + 16 * d < K)
+                        fr[d][rt] = *reinterpret_cast<const v4d*>(Fr + int64_t(row) * a.WFs + kc0 + kb + 16 * d + 4 * lg);
+                }
 #pragma unroll
-                for (int rt = 0; rt < NR; ++rt)
+            for (int d = 0; d < KD; ++d)
 #pragma unroll
-                    for (int ct = 0; ct <= rt; ++ct) acc[e] = mfma(fr[rt][j], fr[ct][j], acc[e]), ++e;
-            }
+                for (int j = 0; j < 4; ++j) {
+                    int e = 0;
+#pragma unroll
+                    for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+                        for (int ct = 0; ct <= rt; ++ct) acc[e] = mfma(fr[d][rt][j], fr[d][ct][j], acc[e]), ++e;
+                }
         }
         // matrix into LDS (lower), identity beyond n
         {
@@ -803,27 +811,39 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 2 : 1)) k_small(KArgs a) {
             if (lane < n) Fr[int64_t(lane) * a.WFs + (a.WF - 1)] = a.z[lo + lane];
             wsync();
         }
-        // solve: columns [tc0, WF) in 16-column tiles, Li (NMAX x NMAX) on the left
-        for (int c0 = tc0; c0 < a.WF; c0 += 16) {
-            const int c = c0 + lr;
-            v4d o[NR];
+        // solve: columns [tc0, WF) in 16-column tiles, CD tiles per batch (their
+        // loads issued together), Li (NMAX x NMAX) on the left
+        constexpr int CD = NMAX <= 32 ? 2 : 1;
+        for (int c0 = tc0; c0 < a.WF; c0 += 16 * CD) {
+            double bv[CD][NMAX / 4];
 #pragma unroll
-            for (int rt = 0; rt < NR; ++rt) o[rt] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int d = 0; d < CD; ++d)
 #pragma unroll
-            for (int ks = 0; ks < NMAX / 4; ++ks) {
-                const int kk = 4 * ks + lg;
-                const double bv = ldg0(Fr, int64_t(kk) * a.WFs + c, kk < n && c < a.WF);
-#pragma unroll
-                for (int rt = 0; rt < NR; ++rt) o[rt] = mfma(Tiw[(16 * rt + lr) * LDT + kk], bv, o[rt]);
-            }
-            wsync();
-#pragma unroll
-            for (int rt = 0; rt < NR; ++rt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * rt + lg + 4 * i;
-                    if (r < n && c < a.WF) Fr[int64_t(r) * a.WFs + c] = o[rt][i];
+                for (int ks = 0; ks < NMAX / 4; ++ks) {
+                    const int kk = 4 * ks + lg, c = c0 + 16 * d + lr;
+                    bv[d][ks] = ldg0(Fr, int64_t(kk) * a.WFs + c, kk < n && c < a.WF);
                 }
+#pragma unroll
+            for (int d = 0; d < CD; ++d) {
+                const int c = c0 + 16 * d + lr;
+                v4d o[NR];
+#pragma unroll
+                for (int rt = 0; rt < NR; ++rt) o[rt] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < NMAX / 4; ++ks) {
+                    const int kk = 4 * ks + lg;
+#pragma unroll
+                    for (int rt = 0; rt < NR; ++rt) o[rt] = mfma(Tiw[(16 * rt + lr) * LDT + kk], bv[d][ks], o[rt]);
+                }
+                wsync();
+#pragma unroll
+                for (int rt = 0; rt < NR; ++rt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = 16 * rt + lg + 4 * i;
+                        if (r < n && c < a.WF) Fr[int64_t(r) * a.WFs + c] = o[rt][i];
+                    }
+            }
         }
         wsync();
     }
