@@ -662,19 +662,28 @@ __global__ void __launch_bounds__(NT) k_prior_finish_w(KArgs a) {
 #pragma unroll
         for (int e = 0; e < NT2; ++e) acc[e] = v4d{0.0, 0.0, 0.0, 0.0};
         const int K = (m - 1) * P;
-        for (int kb = 0; kb < K; kb += 16) {
-            v4d fr[NM];
+        // two k-steps of 16 per batch, their loads issued together (K is a
+        // multiple of 16)
+        for (int kb = 0; kb < K; kb += 32) {
+            v4d fr[2][NM];
 #pragma unroll
-            for (int rt = 0; rt < NM; ++rt)
-                fr[rt] = *reinterpret_cast<const v4d*>(V + int64_t(16 * rt + lr) * ld + kb + 4 * lg);
+            for (int d = 0; d < 2; ++d)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                int e = 0;
+                for (int rt = 0; rt < NM; ++rt) {
+                    fr[d][rt] = v4d{0.0, 0.0, 0.0, 0.0};
+                    if (kb + 16 * d < K)
+                        fr[d][rt] = *reinterpret_cast<const v4d*>(V + int64_t(16 * rt + lr) * ld + kb + 16 * d + 4 * lg);
+                }
 #pragma unroll
-                for (int rt = 0; rt < NM; ++rt)
+            for (int d = 0; d < 2; ++d)
 #pragma unroll
-                    for (int ct = 0; ct <= rt; ++ct) acc[e] = mfma(fr[rt][j], fr[ct][j], acc[e]), ++e;
-            }
+                for (int j = 0; j < 4; ++j) {
+                    int e = 0;
+#pragma unroll
+                    for (int rt = 0; rt < NM; ++rt)
+#pragma unroll
+                        for (int ct = 0; ct <= rt; ++ct) acc[e] = mfma(fr[d][rt][j], fr[d][ct][j], acc[e]), ++e;
+                }
         }
         // W = C - acc into LDS (lower), identity in the padding
         double kx_r[4], ky_r[4];
