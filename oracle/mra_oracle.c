@@ -45,10 +45,15 @@ static int fail(int code, const char *msg) {
     return code;
 }
 
+/* build flags (same values as the library's) */
+#define O_ELIM_DUPLICATES (1u << 1) /* drop repeated locations, keep the first (Sec. 2.2) */
+#define O_ALLOW_ZERO_NUGGET (1u << 2) /* accept tau = 0 in the likelihood */
+
 typedef struct otree {
     int J, M, r, nx, ny, rhat;
     double offset;
-    int64_t n_in, n_nan, n_elim, n_used;
+    uint32_t flags;
+    int64_t n_in, n_nan, n_elim, n_used, n_dup;
     int64_t nreg, nleaf;
     int64_t lvl_start[O_MAXLEV + 1]; /* first level-order index of each level (0-based level) */
     double *box;                     /* nreg x 4 : xlo xhi ylo yhi */
@@ -155,10 +160,21 @@ void oracle_mra_free_tree(otree *t) {
  * (one percent of 1.0 for a degenerate side) unless domain4 is given, which is
  * used verbatim.  An observation that coincides exactly with a knot of one of
  * its ancestors above the finest level is dropped. */
+/* Order of observation indices by location, then input index (for the
+ * duplicate search: equal locations become neighbours, first one first). */
+static const double *g_dx, *g_dy;
+static int cmp_loc(const void *pa, const void *pb) {
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    if (g_dx[a] < g_dx[b]) return -1;
+    if (g_dx[a] > g_dx[b]) return 1;
+    if (g_dy[a] < g_dy[b]) return -1;
+    if (g_dy[a] > g_dy[b]) return 1;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
 int oracle_mra_build_tree(const double *x, const double *y, const double *z, int64_t n, int J,
                           int r, int M, double offset, uint32_t flags, const double *domain4,
                           otree **out) {
-    (void)flags;
     *out = NULL;
     if (n < 0 || (J != 2 && J != 4) || r < 1 || M < 1 || M > O_MAXLEV)
         return fail(O_EINVAL, "bad n/J/r/M");
@@ -167,7 +183,7 @@ int oracle_mra_build_tree(const double *x, const double *y, const double *z, int
         if (!isfinite(x[i]) || !isfinite(y[i])) return fail(O_EINVAL, "non-finite location");
     otree *t = calloc(1, sizeof *t);
     if (!t) return fail(O_ENOMEM, "oom");
-    t->J = J; t->M = M; t->r = r; t->offset = offset;
+    t->J = J; t->M = M; t->r = r; t->offset = offset; t->flags = flags;
     grid_dims(r, &t->nx, &t->ny);
     t->rhat = t->nx * t->ny;
     t->n_in = n;
@@ -203,18 +219,37 @@ int oracle_mra_build_tree(const double *x, const double *y, const double *z, int
                 child_box(t->box + 4 * (t->lvl_start[m] + k), J, j,
                           t->box + 4 * (t->lvl_start[m + 1] + J * k + j));
 
+    /* repeated locations (optional, the ELIMINATION_DUPLICATES_FLAG of
+     * Sec. 2.2): among observations with a value, one whose two coordinates
+     * equal those of an earlier one is dropped; the first is kept */
+    char *dup = calloc(n > 0 ? n : 1, 1);
+    if (!dup) { oracle_mra_free_tree(t); return fail(O_ENOMEM, "oom"); }
+    if (flags & O_ELIM_DUPLICATES) {
+        int64_t *ord = malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+        int64_t nv = 0;
+        for (int64_t i = 0; i < n; i++) if (!isnan(z[i])) ord[nv++] = i;
+        g_dx = x; g_dy = y;
+        qsort(ord, nv, sizeof(int64_t), cmp_loc);
+        for (int64_t s2 = 1; s2 < nv; s2++) {
+            int64_t a = ord[s2 - 1], b = ord[s2];
+            if (x[a] == x[b] && y[a] == y[b]) dup[b] = 1; /* b comes later in the input than a */
+        }
+        free(ord);
+    }
+
     /* assign every observation to its leaf, eliminating knot coincidences */
     int64_t *leaf = malloc(sizeof(int64_t) * (n > 0 ? n : 1));
-    if (!leaf) { oracle_mra_free_tree(t); return fail(O_ENOMEM, "oom"); }
+    if (!leaf) { free(dup); oracle_mra_free_tree(t); return fail(O_ENOMEM, "oom"); }
     double *xb = malloc(sizeof(double) * t->nx), *yb = malloc(sizeof(double) * t->ny);
     int64_t used = 0;
     for (int64_t i = 0; i < n; i++) {
         leaf[i] = -1;
         if (isnan(z[i])) { t->n_nan++; continue; }
         if (x[i] < rb[0] || x[i] >= rb[1] || y[i] < rb[2] || y[i] >= rb[3]) {
-            free(leaf); free(xb); free(yb); oracle_mra_free_tree(t);
+            free(leaf); free(dup); free(xb); free(yb); oracle_mra_free_tree(t);
             return fail(O_EDOMAIN, "observation outside the root domain");
         }
+        if (dup[i]) { t->n_dup++; continue; }
         int64_t k = 0;
         int hit = 0;
         for (int m = 0; m < M; m++) {
@@ -234,7 +269,7 @@ int oracle_mra_build_tree(const double *x, const double *y, const double *z, int
         leaf[i] = k;
         used++;
     }
-    free(xb); free(yb);
+    free(xb); free(yb); free(dup);
     t->n_used = used;
     t->x = malloc(sizeof(double) * (used > 0 ? used : 1));
     t->y = malloc(sizeof(double) * (used > 0 ? used : 1));
@@ -259,6 +294,7 @@ int oracle_mra_build_tree(const double *x, const double *y, const double *z, int
 int oracle_tree_dims(const otree *t, int64_t *v) {
     v[0] = t->n_in; v[1] = t->n_nan; v[2] = t->n_elim; v[3] = t->n_used;
     v[4] = t->nreg; v[5] = t->nleaf; v[6] = t->rhat; v[7] = t->nx; v[8] = t->ny;
+    v[9] = t->n_dup;
     return O_OK;
 }
 int oracle_tree_arrays(const otree *t, double *x, double *y, double *z, int64_t *orig,
@@ -755,7 +791,10 @@ int oracle_mra_loglik(const otree *t, int family, double nu, const double *theta
         ctx->p = t->rhat;
         int rc = make_par(family, nu, theta + 3 * b, &ctx->c);
         if (rc) { free(ctx); return rc; }
-        if (!(ctx->c.tau > 0.0)) { free(ctx); return fail(O_EINVAL, "tau must be positive"); }
+        if (!(ctx->c.tau > 0.0) && !((t->flags & O_ALLOW_ZERO_NUGGET) && ctx->c.tau == 0.0)) {
+            free(ctx);
+            return fail(O_EINVAL, "tau must be positive (zero only with the zero-nugget flag)");
+        }
         double dummyA[1], dummyw[1], du = 0.0;
         if (t->M == 1) {
             visit(ctx, 1, 0, dummyA, dummyw, &du);

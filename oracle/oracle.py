@@ -22,6 +22,8 @@ _SRC = os.path.join(_HERE, "mra_oracle.c")
 _LIB = os.path.join(_HERE, "libmra_oracle.so")
 
 EXP, MATERN = 0, 1
+ELIM_DUPLICATES = 1 << 1
+ALLOW_ZERO_NUGGET = 1 << 2
 
 
 def build(force: bool = False) -> str:
@@ -107,10 +109,10 @@ class Tree:
                                            flags, None if dom is None else _p(dom), C.byref(h)))
         self._h = h
         self.J, self.M, self.r = J, M, r
-        dims = (C.c_int64 * 9)()
+        dims = (C.c_int64 * 10)()
         lib().oracle_tree_dims(h, dims)
         (self.n_in, self.n_nan, self.n_elim, self.n_used, self.nreg, self.nleaf,
-         self.rhat, self.nx, self.ny) = [int(v) for v in dims]
+         self.rhat, self.nx, self.ny, self.n_dup) = [int(v) for v in dims]
 
     def __del__(self):
         h = getattr(self, "_h", None)
