@@ -46,6 +46,9 @@ typedef struct mra_tree mra_tree;
 
 /* mra_build_tree flags */
 #define MRA_DEVICE_PTRS (1u << 0)  /* x, y, z are device pointers (else host) */
+#define MRA_ELIM_DUPLICATES (1u << 1)    /* drop repeated locations, keep the first (Sec. 2.2,
+                                            ELIMINATION_DUPLICATES_FLAG) */
+#define MRA_ALLOW_ZERO_NUGGET (1u << 2)  /* mra_loglik accepts tau = 0 (noise-free data) */
 #define MRA_FOLD_GRAM (1u << 4)    /* fold every region in knot space (Gram form) */
 #define MRA_FOLD_FACTOR (1u << 5)  /* fold in observation space wherever scratch allows */
 
@@ -72,8 +75,12 @@ typedef struct mra_tree mra_tree;
  *   out     : receives an opaque, immutable, library-owned handle; release it
  *             with mra_free_tree.
  * Observations that coincide exactly with a knot of an ancestor region above
- * the finest level are dropped (Sec. 1.2).  Requires a gfx950 device (the
- * current HIP device); the tree's device arrays live on it.
+ * the finest level are dropped (Sec. 1.2).  With MRA_ELIM_DUPLICATES, an
+ * observation whose two coordinates equal (==) those of an earlier observation
+ * with a value is dropped too, the first one kept (Sec. 2.2, the duplicate
+ * elimination user parameter); without it repeated locations stay, and the
+ * likelihood needs a positive nugget.  Requires a gfx950 device (the current
+ * HIP device); the tree's device arrays live on it.
  */
 int mra_build_tree(const double *x, const double *y, const double *z, int64_t n, int J, int r, int M,
                    double offset, uint32_t flags, const double *domain4, mra_tree **out);
@@ -84,7 +91,8 @@ int mra_build_tree(const double *x, const double *y, const double *z, int64_t n,
  * Sigma_MRA is the covariance of tau_1 + ... + tau_M of Sec. 1.1 at the
  * observations, including the -n/2 log(2 pi) constant.
  *   family, nu : MRA_EXP (nu ignored) or MRA_MATERN with nu = 0.5 or 1.5.
- *   theta      : B x 3 row-major {sill alpha, range beta, nugget tau}, all > 0.
+ *   theta      : B x 3 row-major {sill alpha, range beta, nugget tau}, all > 0
+ *                (tau = 0 allowed for a tree built with MRA_ALLOW_ZERO_NUGGET).
  *   loglik     : B outputs.  theta and loglik are both host or both device
  *                pointers.
  *   stream     : hipStream_t (NULL = the null stream).  With device pointers
@@ -92,7 +100,10 @@ int mra_build_tree(const double *x, const double *y, const double *z, int64_t n,
  *                returns after the results are written.
  * The tree is read-only: concurrent calls on different streams are allowed.
  * Errors: MRA_EINVAL (bad family/nu/theta), MRA_ENOTPD (message names theta
- * index, level and region), MRA_ENOMEM, MRA_EDEVICE.
+ * index, level and region), MRA_ENOMEM, MRA_EDEVICE.  With device pointers
+ * the call returns before the kernels run: a theta whose factorisation fails
+ * (or a device theta that is not valid) yields NaN in its output, and
+ * mra_loglik_status reports the failure as MRA_ENOTPD / MRA_EINVAL.
  */
 int mra_loglik(const mra_tree *tree, int family, double nu, const double *theta, int64_t B,
                double *loglik, void *stream);
@@ -108,6 +119,17 @@ int mra_loglik(const mra_tree *tree, int family, double nu, const double *theta,
  */
 int mra_loglik_terms(const mra_tree *tree, int family, double nu, const double *theta, int64_t B,
                      double *loglik, double *logdet, double *quad, void *stream);
+
+/*
+ * Status of the most recent mra_loglik / mra_loglik_terms call on this tree
+ * (for callers that pass device pointers, whose calls return before the
+ * kernels run).  Waits for that call's work on its stream, then returns
+ * MRA_OK, MRA_ENOTPD (a Cholesky pivot was not positive; mra_last_error names
+ * the first such theta index, level and region) or MRA_EINVAL (a theta that
+ * is not finite and positive).  MRA_EINVAL with "no evaluation" if the tree
+ * has none.
+ */
+int mra_loglik_status(const mra_tree *tree);
 
 /*
  * Kriging (prediction mode, Sec. 2.2): posterior mean and variance of the
@@ -133,6 +155,10 @@ typedef struct mra_info {
     int64_t n_regions, n_leaves;
     int64_t leaf_min, leaf_max;          /* observations per finest-level region */
     int64_t n_gram_regions;              /* regions folded in knot space */
+    int64_t n_dup;                       /* repeated locations dropped (MRA_ELIM_DUPLICATES) */
+    int64_t leaf_hist[16];               /* finest-level regions by observation count c:
+                                            [0] c = 0, [b] 2^(b-1) <= c < 2^b (b = 1..14),
+                                            [15] c >= 2^14 */
 } mra_info;
 
 /* Structure summary (the build-structure-only mode of Sec. 2.2). */

@@ -163,6 +163,7 @@ struct mra_tree {
     int WF = 1, WFs = 4;
     Plan lik;  // plan of the likelihood
     int64_t leaf_min = 0, leaf_max = 0;
+    int64_t leaf_hist[16] = {0};
     void* ws = nullptr;  // Workspace*, owned
     ~mra_tree();
 };
@@ -252,13 +253,30 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
     t.gram_tasks.assign(M, {});
     for (int q = 0; q < 3; ++q) t.fsmall_tasks[q].assign(M, {});
     int64_t vo = 0, go = 0;
-    for (int m = 1; m < M; ++m) {
+    // fold form of every region, bottom-up: observation space when the
+    // subtree holds at most the level's threshold AND every child above the
+    // finest level that holds observations folds in observation space too
+    // (an observation-space fold works on its rows' F columns, which only
+    // observation-space descendants keep up to date)
+    for (int m = M - 1; m >= 1; --m) {
         int64_t thr = (gram_only || (flags & MRA_FOLD_GRAM)) ? 0
                       : (flags & MRA_FOLD_FACTOR) ? 4096
                       : std::min<int64_t>(int64_t(m - 1) * P + 1, factor_fold_max());
         if (!gram_only && !(flags & (MRA_FOLD_GRAM | MRA_FOLD_FACTOR)) && opts && m < int64_t(opts->fold_max.size()) &&
             opts->fold_max[m] >= 0)
             thr = opts->fold_max[m];
+        for (int64_t g = h.lvl_start[m - 1]; g < h.lvl_start[m]; ++g) {
+            const int64_t np = h.obs_hi[g] - h.obs_lo[g];
+            bool fac = np <= thr;
+            if (fac && m + 1 < M)
+                for (int j = 0; j < h.J; ++j) {
+                    const int64_t gc = h.lvl_start[m] + (g - h.lvl_start[m - 1]) * h.J + j;
+                    if (h.obs_hi[gc] > h.obs_lo[gc] && t.form[gc] != FOLD_FACTOR) fac = false;
+                }
+            t.form[g] = fac ? FOLD_FACTOR : FOLD_GRAM;
+        }
+    }
+    for (int m = 1; m < M; ++m) {
         const int64_t D = int64_t(m) * P + 1;
         for (int64_t g = h.lvl_start[m - 1]; g < h.lvl_start[m]; ++g) {
             const int64_t np = h.obs_hi[g] - h.obs_lo[g];
@@ -268,8 +286,7 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
             t.vst_off[g] = vo;
             vo += int64_t(m) * P * P;
             if (np == 0) continue;             // prior only (prediction points below)
-            if (np <= thr) {
-                t.form[g] = FOLD_FACTOR;
+            if (t.form[g] == FOLD_FACTOR) {
                 if (np <= 16 && np <= smax) t.fsmall_tasks[0][m].push_back(int(g));
                 else if (np <= 32 && np <= smax) t.fsmall_tasks[1][m].push_back(int(g));
                 else if (np <= 64 && np <= smax) t.fsmall_tasks[2][m].push_back(int(g));
@@ -279,7 +296,6 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
                     t.scratch_fold = std::max(t.scratch_fold, np * np + ((np + 63) / 64) * 4096);
                 }
             } else {
-                t.form[g] = FOLD_GRAM;
                 t.gram_tasks[m].push_back(int(g));
                 t.gram_off[g] = go;
                 go += D * D;
@@ -355,7 +371,7 @@ hipEvent_t pooled_event() {
 }
 const char* const KIND_NAMES[] = {"k_chain",     "k_prior_finish", "k_leaf_finish", "k_fold_factor",
                                   "k_gram_panel", "k_final",       "k_small_leaf",  "k_small_fold",
-                                  "k_pred_leaf",  "k_pred_fold",   "k_gram_tile"};
+                                  "k_pred_leaf",  "k_pred_fold",   "k_gram_tile",  "k_gram_tile2"};
 }  // namespace
 
 template <class F>
@@ -455,7 +471,7 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
     t->flags = flags;
     (void)hipGetDevice(&t->device);
     std::string err;
-    rc = build_host_tree(px, py, pz, n, J, r, M, offset, domain4, t->h, err);
+    rc = build_host_tree(px, py, pz, n, J, r, M, offset, flags, domain4, t->h, err);
     if (rc) { delete t; return fail(rc, err); }
     const HostTree& h = t->h;
     if (M - 1 > chain_lmax(h.P)) {
@@ -470,6 +486,9 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
         const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
         t->leaf_min = std::min(t->leaf_min, nc);
         t->leaf_max = std::max(t->leaf_max, nc);
+        int b = 0;
+        while (b < 15 && (int64_t(1) << b) <= nc) ++b;  // 2^(b-1) <= nc < 2^b
+        ++t->leaf_hist[b];
     }
     if (t->leaf_min == INT64_MAX) t->leaf_min = 0;
     t->opts.fold_max.assign(M, -1);
@@ -495,6 +514,8 @@ extern "C" int mra_tree_info(const mra_tree* t, mra_info* info) {
     info->n_regions = h.nreg; info->n_leaves = h.nleaf;
     info->leaf_min = t->leaf_min; info->leaf_max = t->leaf_max;
     info->n_gram_regions = t->lik.n_gram;
+    info->n_dup = h.n_dup;
+    for (int b = 0; b < 16; ++b) info->leaf_hist[b] = t->leaf_hist[b];
     return MRA_OK;
 }
 
@@ -527,8 +548,22 @@ static int region_level(const HostTree& h, int64_t g) {
     return h.M;
 }
 
-static bool theta_ok(const double* q) {
-    return q[0] > 0.0 && q[1] > 0.0 && q[2] > 0.0 && std::isfinite(q[0]) && std::isfinite(q[1]) && std::isfinite(q[2]);
+// MRA_OK, or MRA_ENOTPD naming the first theta whose factorisation failed
+// (status: per theta 0 or 1 + the global index of the failing region).
+static int status_message(const HostTree& h, const int* status, int64_t B) {
+    for (int64_t b = 0; b < B; ++b)
+        if (status[b] != 0) {
+            const int64_t g = status[b] - 1;
+            const int lev = region_level(h, g);
+            return fail(MRA_ENOTPD, "not positive definite: theta " + std::to_string(b) + ", level " +
+                                        std::to_string(lev) + ", region " + std::to_string(g - h.lvl_start[lev - 1]));
+        }
+    return MRA_OK;
+}
+
+static bool theta_ok(const double* q, bool zero_nugget = false) {
+    return q[0] > 0.0 && q[1] > 0.0 && (q[2] > 0.0 || (zero_nugget && q[2] == 0.0)) && std::isfinite(q[0]) &&
+           std::isfinite(q[1]) && std::isfinite(q[2]);
 }
 
 // Kernel arguments common to every launch over a tree and plan.
@@ -546,6 +581,7 @@ static KArgs base_args(const mra_tree* t, const Plan& pl, int smooth) {
     a.gram_stride = pl.gram_size;
     a.d_stride = h.nreg;
     a.n_used = double(h.n_used);
+    a.zero_nugget = (t->flags & MRA_ALLOW_ZERO_NUGGET) ? 1 : 0;
     return a;
 }
 
@@ -621,7 +657,7 @@ static hipError_t enqueue_fold(const mra_tree* t, const Plan& pl, KArgs a, int m
                  return launch_gram_panel(a, int(std::min<int64_t>(a.ntasks * nb, 1 << 16)), st);
              })))
             return e;
-        if (m > 1 && (e = timed(10, m, pl.fl_gtile[m] * nb, st, [&] {
+        if (m > 1 && (e = timed(pl.gtile_super[m] ? 11 : 10, m, pl.fl_gtile[m] * nb, st, [&] {
                           return pl.gtile_super[m] ? launch_gram_tile2(a, st) : launch_gram_tile(a, st);
                       })))
             return e;
@@ -650,6 +686,8 @@ struct Workspace {
     hipEvent_t done = nullptr;
     hipStream_t last = nullptr;
     bool used = false;
+    int64_t last_B = 0;          // theta of the most recent evaluation (its status in `status`)
+    const double* last_th = nullptr;  // its device theta
     // captured graphs of whole evaluations, keyed by (theta, out, logdet, quad, B, smooth, stream)
     std::map<std::tuple<const void*, void*, void*, void*, int64_t, int, void*>, hipGraphExec_t> graphs;
     void drop_graphs() {
@@ -778,10 +816,12 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
     const bool dev = is_device_ptr(theta);
     if (dev != is_device_ptr(loglik) || (logdet && dev != is_device_ptr(logdet)) || (quad && dev != is_device_ptr(quad)))
         return fail(MRA_EINVAL, "theta, loglik, logdet and quad must be in the same memory space");
+    const bool zn = (t->flags & MRA_ALLOW_ZERO_NUGGET) != 0;
     if (!dev)
         for (int64_t b = 0; b < B; ++b)
-            if (!theta_ok(theta + 3 * b))
-                return fail(MRA_EINVAL, "theta " + std::to_string(b) + ": alpha, beta, tau must be finite and > 0");
+            if (!theta_ok(theta + 3 * b, zn))
+                return fail(MRA_EINVAL, "theta " + std::to_string(b) + ": alpha, beta, tau must be finite and > 0" +
+                                            (zn ? " (tau >= 0)" : ""));
 
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace& w = workspace_of(t);
@@ -828,6 +868,8 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
     (void)hipEventRecord(w.done, st);
     w.last = st;
     w.used = true;
+    w.last_B = B;
+    w.last_th = d_th;
     if (!dev) {
         HIPCHK(hipMemcpyAsync(loglik, d_out, B * 8, hipMemcpyDeviceToHost, st));
         if (logdet) HIPCHK(hipMemcpyAsync(logdet, d_ld, B * 8, hipMemcpyDeviceToHost, st));
@@ -835,17 +877,29 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
         hstatus.resize(B);
         HIPCHK(hipMemcpyAsync(hstatus.data(), w.status, B * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        for (int64_t b = 0; b < B; ++b)
-            if (hstatus[b] != 0) {
-                const int64_t g = hstatus[b] - 1;
-                const int lev = region_level(h, g);
-                rc = fail(MRA_ENOTPD, "not positive definite: theta " + std::to_string(b) + ", level " +
-                                          std::to_string(lev) + ", region " + std::to_string(g - h.lvl_start[lev - 1]));
-                break;
-            }
+        rc = status_message(h, hstatus.data(), B);
     }
 done:
     return rc;
+}
+
+extern "C" int mra_loglik_status(const mra_tree* t) {
+    if (!t) return fail(MRA_EINVAL, "NULL tree");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if (!t->ws) return fail(MRA_EINVAL, "no evaluation on this tree");
+    Workspace& w = *static_cast<Workspace*>(t->ws);
+    if (!w.used || w.last_B < 1) return fail(MRA_EINVAL, "no evaluation on this tree");
+    if (hipEventSynchronize(w.done) != hipSuccess) return fail(MRA_EDEVICE, "waiting for the evaluation failed");
+    std::vector<int> hs(w.last_B);
+    std::vector<double> th(3 * w.last_B);
+    if (hipMemcpy(hs.data(), w.status, w.last_B * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(th.data(), w.last_th, 3 * w.last_B * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(MRA_EDEVICE, "copy of the evaluation status failed");
+    const bool zn = (t->flags & MRA_ALLOW_ZERO_NUGGET) != 0;
+    for (int64_t b = 0; b < w.last_B; ++b)
+        if (!theta_ok(&th[3 * b], zn))
+            return fail(MRA_EINVAL, "theta " + std::to_string(b) + ": alpha, beta, tau must be finite and > 0");
+    return status_message(t->h, hs.data(), w.last_B);
 }
 
 extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double* theta, int64_t B,
@@ -887,13 +941,20 @@ extern "C" int mra_set_plan(mra_tree* t, const int64_t* fold_max, int small_max)
     return replan(t);
 }
 
-// Form of every level-m region under a candidate threshold (to skip
-// candidates that change nothing).
-static std::vector<int8_t> level_forms(const HostTree& h, int m, int64_t thr) {
+// Form of every level-m region under a candidate threshold, given the forms
+// of the level below in the installed plan (to skip candidates that change
+// nothing); the same rule as make_plan.
+static std::vector<int8_t> level_forms(const HostTree& h, const std::vector<int8_t>& form, int m, int64_t thr) {
     std::vector<int8_t> f;
     for (int64_t g = h.lvl_start[m - 1]; g < h.lvl_start[m]; ++g) {
         const int64_t np = h.obs_hi[g] - h.obs_lo[g];
-        f.push_back(np == 0 ? int8_t(2) : (np <= thr ? int8_t(FOLD_FACTOR) : int8_t(FOLD_GRAM)));
+        bool fac = np <= thr;
+        if (fac && m + 1 < h.M)
+            for (int j = 0; j < h.J; ++j) {
+                const int64_t gc = h.lvl_start[m] + (g - h.lvl_start[m - 1]) * h.J + j;
+                if (h.obs_hi[gc] > h.obs_lo[gc] && form[gc] != FOLD_FACTOR) fac = false;
+            }
+        f.push_back(np == 0 ? int8_t(2) : (fac ? int8_t(FOLD_FACTOR) : int8_t(FOLD_GRAM)));
     }
     return f;
 }
@@ -933,10 +994,10 @@ extern "C" int mra_autotune(mra_tree* t, int family, double nu, const double* th
     for (int m = M - 1; m >= 1; --m) {
         const int64_t keep = t->opts.fold_max[m];
         const int64_t cur_thr = keep >= 0 ? keep : std::min<int64_t>(int64_t(m - 1) * h.P + 1, factor_fold_max());
-        std::vector<std::vector<int8_t>> seen{level_forms(h, m, cur_thr)};
+        std::vector<std::vector<int8_t>> seen{level_forms(h, t->lik.form, m, cur_thr)};
         int64_t best_v = keep;
         for (int64_t c : cands) {
-            auto f = level_forms(h, m, c);
+            auto f = level_forms(h, t->lik.form, m, c);
             if (std::find(seen.begin(), seen.end(), f) != seen.end()) continue;
             seen.push_back(f);
             t->opts.fold_max[m] = c;

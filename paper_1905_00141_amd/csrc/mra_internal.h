@@ -16,7 +16,7 @@ enum FoldForm : int8_t { FOLD_FACTOR = 0, FOLD_GRAM = 1 };
 struct HostTree {
     int J = 4, M = 1, r = 1, nx = 1, ny = 1, rhat = 1, P = 16;
     double offset = 0.0;
-    int64_t n_in = 0, n_nan = 0, n_elim = 0, n_used = 0;
+    int64_t n_in = 0, n_nan = 0, n_elim = 0, n_used = 0, n_dup = 0;
     int64_t nreg = 0, nleaf = 0;
     std::vector<int64_t> lvl_start;  // M + 1 entries
     std::vector<double> box;         // nreg * 4 (xlo, xhi, ylo, yhi)
@@ -28,7 +28,7 @@ struct HostTree {
 
 // Builds the partition on the host.  Returns an MRA_* status, message in err.
 int build_host_tree(const double* x, const double* y, const double* z, int64_t n, int J, int r,
-                    int M, double offset, const double* domain4, HostTree& t, std::string& err);
+                    int M, double offset, uint32_t flags, const double* domain4, HostTree& t, std::string& err);
 
 }  // namespace mra
 

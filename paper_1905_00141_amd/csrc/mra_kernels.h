@@ -53,6 +53,7 @@ struct KArgs {
     double* out_ld;           // final (optional): sum of log-determinants per theta
     double* out_q;            // final (optional): quadratic form per theta
     double n_used;
+    int zero_nugget;          // 1: tau = 0 is a valid nugget
     // prediction (one theta): points grouped by leaf
     const double* px;
     const double* py;

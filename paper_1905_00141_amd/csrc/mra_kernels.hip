@@ -1546,8 +1546,8 @@ __global__ void __launch_bounds__(NT) k_final(KArgs a, int64_t nreg, int root_gr
         const double LOG2PI = 1.8378770664093454835606594728112;
         double ll = -0.5 * (a.n_used * LOG2PI + dsum + q);
         const double* thp = a.theta + 3 * th;
-        const bool ok = thp[0] > 0.0 && thp[1] > 0.0 && thp[2] > 0.0 && thp[0] < 1.0 / 0.0 && thp[1] < 1.0 / 0.0 &&
-                        thp[2] < 1.0 / 0.0;
+        const bool ok = thp[0] > 0.0 && thp[1] > 0.0 && (thp[2] > 0.0 || (a.zero_nugget && thp[2] == 0.0)) &&
+                        thp[0] < 1.0 / 0.0 && thp[1] < 1.0 / 0.0 && thp[2] < 1.0 / 0.0;
         const bool bad = a.status[th] != 0 || !ok;
         if (bad) ll = __builtin_nan("");
         a.out[th] = ll;

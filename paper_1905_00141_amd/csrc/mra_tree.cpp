@@ -2,6 +2,7 @@
 // Compiled with -ffp-contract=off so that midpoints and knot bars are the
 // plain IEEE results of the expressions below; the knot-coincidence test
 // compares observations with knots bit for bit.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -57,7 +58,7 @@ Box child(const Box& b, int J, int j) {
 }  // namespace
 
 int build_host_tree(const double* x, const double* y, const double* z, int64_t n, int J, int r,
-                    int M, double offset, const double* domain4, HostTree& t, std::string& err) {
+                    int M, double offset, uint32_t flags, const double* domain4, HostTree& t, std::string& err) {
     if (n < 0 || (J != 2 && J != 4) || r < 1 || M < 1 || M > 16) {
         err = "invalid n, J (2 or 4), r (>= 1) or M (1..16)";
         return MRA_EINVAL;
@@ -120,17 +121,35 @@ int build_host_tree(const double* x, const double* y, const double* z, int64_t n
             for (int j = 0; j < J; ++j) put(t.lvl_start[m + 1] + J * k + j, child(b, J, j));
         }
 
-    // leaf of every observation; drop NaN values and knot coincidences
+    // repeated locations: observations (with a value) sorted by location, then
+    // input index; every later member of a run of equal locations is a repeat
+    std::vector<char> rep(n, 0);
+    if (flags & MRA_ELIM_DUPLICATES) {
+        std::vector<int64_t> ord;
+        ord.reserve(n);
+        for (int64_t i = 0; i < n; ++i)
+            if (!std::isnan(z[i])) ord.push_back(i);
+        std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+            if (x[a] != x[b]) return x[a] < x[b];
+            if (y[a] != y[b]) return y[a] < y[b];
+            return a < b;
+        });
+        for (size_t s = 1; s < ord.size(); ++s)
+            if (x[ord[s]] == x[ord[s - 1]] && y[ord[s]] == y[ord[s - 1]]) rep[ord[s]] = 1;
+    }
+
+    // leaf of every observation; drop NaN values, repeats and knot coincidences
     std::vector<int64_t> leaf(n, -1);
     std::vector<double> xb(nx), yb(ny);
     int64_t used = 0;
-    t.n_nan = t.n_elim = 0;
+    t.n_nan = t.n_elim = t.n_dup = 0;
     for (int64_t i = 0; i < n; ++i) {
         if (std::isnan(z[i])) { ++t.n_nan; continue; }
         if (x[i] < root.xlo || x[i] >= root.xhi || y[i] < root.ylo || y[i] >= root.yhi) {
             err = "observation " + std::to_string(i) + " lies outside the root region";
             return MRA_EDOMAIN;
         }
+        if (rep[i]) { ++t.n_dup; continue; }
         int64_t k = 0;
         bool on_knot = false;
         for (int m = 0; m + 1 < M; ++m) {

@@ -18,10 +18,12 @@ LIB_PATH = os.path.join(HERE, "libmra.so")
 MRA_OK, MRA_EINVAL, MRA_ENOTPD, MRA_ENOMEM, MRA_EDEVICE, MRA_EDOMAIN = 0, -1, -2, -3, -4, -5
 MRA_EXP, MRA_MATERN = 0, 1
 MRA_DEVICE_PTRS = 1 << 0
+MRA_ELIM_DUPLICATES = 1 << 1
+MRA_ALLOW_ZERO_NUGGET = 1 << 2
 MRA_FOLD_GRAM = 1 << 4
 MRA_FOLD_FACTOR = 1 << 5
 
-EXPORTED = ["mra_build_tree", "mra_loglik", "mra_loglik_terms", "mra_predict", "mra_free_tree", "mra_last_error",
+EXPORTED = ["mra_build_tree", "mra_loglik", "mra_loglik_terms", "mra_loglik_status", "mra_predict", "mra_free_tree", "mra_last_error",
             "mra_tree_info", "mra_tree_arrays", "mra_profile_enable", "mra_profile_read",
             "mra_autotune", "mra_set_plan",
             "mra_mlp_create", "mra_mlp_set_scaling", "mra_mlp_forward", "mra_mlp_loss_grad",
@@ -34,7 +36,8 @@ class MraInfo(C.Structure):
     _fields_ = [("n_in", C.c_int64), ("n_nan", C.c_int64), ("n_elim", C.c_int64), ("n_used", C.c_int64),
                 ("J", C.c_int32), ("M", C.c_int32), ("r", C.c_int32), ("r_hat", C.c_int32), ("P", C.c_int32),
                 ("n_regions", C.c_int64), ("n_leaves", C.c_int64), ("leaf_min", C.c_int64),
-                ("leaf_max", C.c_int64), ("n_gram_regions", C.c_int64)]
+                ("leaf_max", C.c_int64), ("n_gram_regions", C.c_int64), ("n_dup", C.c_int64),
+                ("leaf_hist", C.c_int64 * 16)]
 
 
 class TuneResult(C.Structure):
@@ -65,6 +68,8 @@ def load_library(path: str = LIB_PATH):
     L.mra_loglik.restype = C.c_int
     L.mra_loglik_terms.argtypes = [vp, C.c_int, C.c_double, pd, i64, pd, pd, pd, vp]
     L.mra_loglik_terms.restype = C.c_int
+    L.mra_loglik_status.argtypes = [vp]
+    L.mra_loglik_status.restype = C.c_int
     L.mra_predict.argtypes = [vp, C.c_int, C.c_double, pd, pd, pd, i64, pd, pd, vp]
     L.mra_predict.restype = C.c_int
     L.mra_free_tree.argtypes = [vp]
@@ -176,6 +181,7 @@ class Tree:
         info = MraInfo()
         _check(_lib.mra_tree_info(h, C.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in MraInfo._fields_}
+        self.info["leaf_hist"] = list(info.leaf_hist)
         self.n_used = info.n_used
         self.M, self.J, self.r_hat, self.P = info.M, info.J, info.r_hat, info.P
 
@@ -210,6 +216,11 @@ class Tree:
         _check(_lib.mra_loglik(self._h, family_code(family), float(nu), _ptr(th), B, _ptr(res),
                                _stream_ptr(stream)))
         return res
+
+    def status(self):
+        """Wait for the most recent evaluation and raise MraError if it failed
+        (mra_loglik_status; for calls made with device pointers)."""
+        _check(_lib.mra_loglik_status(self._h))
 
     def autotune(self, theta, family="matern", nu=0.5):
         """Time candidate execution plans on a host sample of theta and install the fastest."""
