@@ -1,6 +1,8 @@
 """Builds libmra.so (HIP kernels for gfx950 + host code) in-tree.
 
-    python -m paper_1905_00141_amd.build
+    python -m paper_1905_00141_amd.build [--changed]
+
+--changed recompiles only the sources newer than their objects.
 """
 from __future__ import annotations
 
@@ -33,21 +35,34 @@ def _run(cmd):
     return r
 
 
-def build(verbose: bool = False) -> str:
+def _stale(obj: str, src: str) -> bool:
+    """An object is rebuilt when it is older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")] + \
+        [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, force: bool = True) -> str:
+    """Compile every source (force) or only those changed since their object."""
     os.makedirs(BUILD_DIR, exist_ok=True)
     jobs = []
     objs = []
     for s in HIP_SOURCES:
         o = os.path.join(BUILD_DIR, s + ".o")
         objs.append(o)
-        jobs.append([HIPCC] + HIP_FLAGS + ["-c", "-o", o, os.path.join(CSRC, s)])
+        if force or _stale(o, os.path.join(CSRC, s)):
+            jobs.append([HIPCC] + HIP_FLAGS + ["-c", "-o", o, os.path.join(CSRC, s)])
     for s in HOST_SOURCES:
         o = os.path.join(BUILD_DIR, s + ".o")
         objs.append(o)
         # host-only tree builder: plain IEEE expression evaluation (no FMA contraction)
-        jobs.append(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off",
-                     "-I" + INCLUDE, "-I" + CSRC, "-c", "-o", o, os.path.join(CSRC, s)])
-    with ThreadPoolExecutor(max_workers=4) as ex:
+        if force or _stale(o, os.path.join(CSRC, s)):
+            jobs.append(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=off",
+                         "-I" + INCLUDE, "-I" + CSRC, "-c", "-o", o, os.path.join(CSRC, s)])
+    with ThreadPoolExecutor(max_workers=8) as ex:
         list(ex.map(_run, jobs))
     tmp = OUT + ".tmp"
     _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
@@ -58,4 +73,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, force="--changed" not in sys.argv)
