@@ -121,6 +121,27 @@ int mra_loglik_terms(const mra_tree *tree, int family, double nu, const double *
                      double *loglik, double *logdet, double *quad, void *stream);
 
 /*
+ * mra_loglik for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * same kernels as mra_loglik, but every buffer beyond the inputs and outputs
+ * lives in one fixed array of 64 MiB of device memory per GPU, created when
+ * the library is loaded and held until the process ends; this call allocates
+ * nothing and creates no HIP object.
+ *   theta, loglik : device pointers (B x 3 and B), on the tree's device, which
+ *                   must be the current device; the call is asynchronous on
+ *                   `stream`.
+ * Trees whose one-theta working set (V stores, finest-level factors, Gram
+ * blocks, one workgroup slot) exceeds 64 MiB -> MRA_ENOMEM, with the size in
+ * the message (a tree of a few thousand observations at r = 32 fits; the
+ * theta batch is processed in chunks that fit).  Every call on a GPU uses that
+ * GPU's array: calls that overlap in time on one GPU (different streams or
+ * threads) race and must be serialised by the caller.  A failed factorisation
+ * gives NaN for that theta (no status is kept).
+ */
+int mra_loglik_noalloc(const mra_tree *tree, int family, double nu, const double *theta, int64_t B,
+                       double *loglik, void *stream);
+
+/*
  * Status of the most recent mra_loglik / mra_loglik_terms call on this tree
  * (for callers that pass device pointers, whose calls return before the
  * kernels run).  Waits for that call's work on its stream, then returns

@@ -374,8 +374,13 @@ const char* const KIND_NAMES[] = {"k_chain",     "k_prior_finish", "k_leaf_finis
                                   "k_pred_leaf",  "k_pred_fold",   "k_gram_tile",  "k_gram_tile2"};
 }  // namespace
 
+// Set while an entry point that must not create HIP objects enqueues its
+// launches (per-launch timing would create events).
+thread_local bool t_untimed = false;
+
 template <class F>
 static hipError_t timed(int kind, int level, double flops, hipStream_t st, F&& launch) {
+    if (t_untimed) return launch();
     bool on;
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -773,26 +778,28 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
     return MRA_OK;
 }
 
-// Every launch of one evaluation of B parameter vectors (chunks of Bc).
-static hipError_t enqueue_loglik(const mra_tree* t, Workspace& w, KArgs a, const double* d_th, double* d_out,
-                                 double* d_ld, double* d_q, int* status, int64_t B, hipStream_t st) {
+// Every launch of one evaluation of B parameter vectors, in chunks of Bc
+// theta (the per-theta buffers of a.vst, a.F, a.gram, a.dval hold Bc theta;
+// nslot workgroup slots of a.scratch).
+static hipError_t enqueue_loglik(const mra_tree* t, int64_t Bc, int64_t nslot, KArgs a, const double* d_th,
+                                 double* d_out, double* d_ld, double* d_q, int* status, int64_t B, hipStream_t st) {
     const HostTree& h = t->h;
     const Plan& pl = t->lik;
     hipError_t e;
     if ((e = launch_fill_int(status, B, 0, st))) return e;
-    for (int64_t b0 = 0; b0 < B; b0 += w.Bc) {
-        const int nb = int(std::min<int64_t>(w.Bc, B - b0));
+    for (int64_t b0 = 0; b0 < B; b0 += Bc) {
+        const int nb = int(std::min<int64_t>(Bc, B - b0));
         a.theta = d_th + 3 * b0;
         a.ntheta = nb;
         a.status = status + b0;
         a.out = d_out + b0;
         a.out_ld = d_ld ? d_ld + b0 : nullptr;
         a.out_q = d_q ? d_q + b0 : nullptr;
-        if ((e = launch_fill(w.dval, int64_t(nb) * h.nreg, 0.0, st))) return e;
+        if ((e = launch_fill(a.dval, int64_t(nb) * a.d_stride, 0.0, st))) return e;
         if ((e = enqueue_prior(t, pl, a, nb, st))) return e;
-        if ((e = enqueue_leaves(t, pl, a, nb, w.nslot, st))) return e;
+        if ((e = enqueue_leaves(t, pl, a, nb, nslot, st))) return e;
         for (int m = h.M - 1; m >= 1; --m)
-            if ((e = enqueue_fold(t, pl, a, m, nb, w.nslot, st))) return e;
+            if ((e = enqueue_fold(t, pl, a, m, nb, nslot, st))) return e;
         if ((e = timed(5, 0, 0.0, st, [&] { return launch_final(a, h.nreg, pl.root_gram, st); }))) return e;
     }
     return hipSuccess;
@@ -852,7 +859,7 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
             HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            const hipError_t ce = enqueue_loglik(t, w, a, d_th, d_out, d_ld, d_q, w.status, B, st);
+            const hipError_t ce = enqueue_loglik(t, w.Bc, w.nslot, a, d_th, d_out, d_ld, d_q, w.status, B, st);
             const hipError_t ee = hipStreamEndCapture(st, &g);
             HIPCHK(ce);
             HIPCHK(ee);
@@ -863,7 +870,7 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
         }
         HIPCHK(hipGraphLaunch(it->second, st));
     } else {
-        HIPCHK(enqueue_loglik(t, w, a, d_th, d_out, d_ld, d_q, w.status, B, st));
+        HIPCHK(enqueue_loglik(t, w.Bc, w.nslot, a, d_th, d_out, d_ld, d_q, w.status, B, st));
     }
     (void)hipEventRecord(w.done, st);
     w.last = st;
@@ -910,6 +917,85 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
 extern "C" int mra_loglik_terms(const mra_tree* t, int family, double nu, const double* theta, int64_t B,
                                 double* loglik, double* logdet, double* quad, void* stream) {
     return loglik_impl(t, family, nu, theta, B, loglik, logdet, quad, stream);
+}
+
+// ------------------------------------------- evaluation without allocation
+
+// Device memory of mra_loglik_noalloc: one array per GPU, kept until the
+// process ends.  In host code `scratch` is only a symbol; its device address
+// is looked up once per device (hipGetSymbolAddress) and that address is what
+// the kernels receive.
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;
+static __device__ __align__(256) double scratch[NOALLOC_BYTES / sizeof(double)];
+
+static std::mutex g_noalloc_mu;
+static void* g_noalloc_ptr[64] = {nullptr};
+
+static int noalloc_base(int dev, double** out) {
+    if (dev < 0 || dev >= 64) return fail(MRA_EDEVICE, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MRA_EDEVICE, std::string("hipGetSymbolAddress of the scratch array failed: ") +
+                                         hipGetErrorString(e));
+        g_noalloc_ptr[dev] = p;
+    }
+    *out = static_cast<double*>(g_noalloc_ptr[dev]);
+    return MRA_OK;
+}
+
+extern "C" int mra_loglik_noalloc(const mra_tree* t, int family, double nu, const double* theta, int64_t B,
+                                  double* loglik, void* stream) {
+    if (!t || !theta || !loglik || B < 1) return fail(MRA_EINVAL, "NULL argument or B < 1");
+    int smooth = 0;
+    int rc = smooth_of(family, nu, &smooth);
+    if (rc) return rc;
+    if (!is_device_ptr(theta) || !is_device_ptr(loglik))
+        return fail(MRA_EINVAL, "mra_loglik_noalloc takes device pointers for theta and loglik");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MRA_EDEVICE, "hipGetDevice failed");
+    if (dev != t->device) return fail(MRA_EINVAL, "the current device is not the tree's device");
+    double* base = nullptr;
+    if ((rc = noalloc_base(dev, &base))) return rc;
+    const HostTree& h = t->h;
+    const Plan& pl = t->lik;
+    // layout (doubles, each part 256-byte aligned): status (B ints), then
+    // Bc theta of V stores, F rows, Gram blocks and log-determinants, then
+    // nslot workgroup slots
+    auto al32 = [](int64_t v) { return (v + 31) & ~int64_t(31); };
+    const int64_t cap = int64_t(NOALLOC_BYTES / sizeof(double));
+    const int64_t st_sz = al32((B * int64_t(sizeof(int)) + 7) / 8);
+    const int64_t F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
+    const int64_t per_theta = al32(pl.vst_size) + al32(F_stride) + al32(pl.gram_size) + al32(h.nreg);
+    const int64_t slot = al32(std::max<int64_t>({pl.scratch_leaf, pl.scratch_fold, 1}));
+    int64_t nslot = 256;
+    while (nslot > 1 && st_sz + per_theta + nslot * slot > cap) nslot /= 2;
+    if (st_sz + per_theta + nslot * slot > cap)
+        return fail(MRA_ENOMEM, "mra_loglik_noalloc: one theta of this tree needs " +
+                                    std::to_string((st_sz + per_theta + slot) * 8) + " bytes of scratch, the limit is " +
+                                    std::to_string(NOALLOC_BYTES) + " bytes");
+    const int64_t Bc = std::min<int64_t>(B, (cap - st_sz - nslot * slot) / per_theta);
+    KArgs a = base_args(t, pl, smooth);
+    int* status = reinterpret_cast<int*>(base);
+    double* p = base + st_sz;
+    a.vst = p; p += Bc * al32(pl.vst_size);
+    a.F = p; p += Bc * al32(F_stride);
+    a.gram = p; p += Bc * al32(pl.gram_size);
+    a.dval = p; p += Bc * al32(h.nreg);
+    a.scratch = p;
+    a.scratch_stride = slot;
+    a.vst_stride = al32(pl.vst_size);
+    a.F_stride = al32(F_stride);
+    a.gram_stride = al32(pl.gram_size);
+    a.d_stride = al32(h.nreg);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    t_untimed = true;
+    const hipError_t e = enqueue_loglik(t, Bc, nslot, a, theta, loglik, nullptr, nullptr, status, B, st);
+    t_untimed = false;
+    if (e != hipSuccess) return fail(MRA_EDEVICE, std::string("launch failed: ") + hipGetErrorString(e));
+    return MRA_OK;
 }
 
 // ------------------------------------------------------------- autotuning

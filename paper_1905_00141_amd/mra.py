@@ -23,7 +23,8 @@ MRA_ALLOW_ZERO_NUGGET = 1 << 2
 MRA_FOLD_GRAM = 1 << 4
 MRA_FOLD_FACTOR = 1 << 5
 
-EXPORTED = ["mra_build_tree", "mra_loglik", "mra_loglik_terms", "mra_loglik_status", "mra_predict", "mra_free_tree", "mra_last_error",
+EXPORTED = ["mra_build_tree", "mra_loglik", "mra_loglik_terms", "mra_loglik_status", "mra_loglik_noalloc",
+            "mra_predict", "mra_free_tree", "mra_last_error",
             "mra_tree_info", "mra_tree_arrays", "mra_profile_enable", "mra_profile_read",
             "mra_autotune", "mra_set_plan",
             "mra_mlp_create", "mra_mlp_set_scaling", "mra_mlp_forward", "mra_mlp_loss_grad",
@@ -68,6 +69,8 @@ def load_library(path: str = LIB_PATH):
     L.mra_loglik.restype = C.c_int
     L.mra_loglik_terms.argtypes = [vp, C.c_int, C.c_double, pd, i64, pd, pd, pd, vp]
     L.mra_loglik_terms.restype = C.c_int
+    L.mra_loglik_noalloc.argtypes = [vp, C.c_int, C.c_double, pd, i64, pd, vp]
+    L.mra_loglik_noalloc.restype = C.c_int
     L.mra_loglik_status.argtypes = [vp]
     L.mra_loglik_status.restype = C.c_int
     L.mra_predict.argtypes = [vp, C.c_int, C.c_double, pd, pd, pd, i64, pd, pd, vp]
@@ -216,6 +219,12 @@ class Tree:
         _check(_lib.mra_loglik(self._h, family_code(family), float(nu), _ptr(th), B, _ptr(res),
                                _stream_ptr(stream)))
         return res
+
+    def loglik_noalloc(self, theta, out, family="matern", nu=0.5, stream=None):
+        """mra_loglik_noalloc: device theta (B, 3) and device out (B,), no allocation."""
+        _check(_lib.mra_loglik_noalloc(self._h, family_code(family), float(nu), _ptr(theta), theta.shape[0],
+                                       _ptr(out), _stream_ptr(stream)))
+        return out
 
     def status(self):
         """Wait for the most recent evaluation and raise MraError if it failed
