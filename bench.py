@@ -88,10 +88,17 @@ def cpu_baseline(cfg, theta, budget_s=25.0):
     }
 
 
+KERNEL_SOURCES = ["mra_device.h", "mra_chain.hip", "mra_finish.hip", "mra_gram.hip"]
+
+
 def kernel_source_digest():
+    """SHA-256 (16 hex digits) of the log-likelihood kernels' sources."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_1905_00141_amd", "csrc", "mra_kernels.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1905_00141_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(name, level):

@@ -1,0 +1,542 @@
+// Knot-space folds, the final log-likelihood sum and fills.
+#include "mra_device.h"
+
+namespace mra {
+
+// Knot-space fold in two launches.  With D = mP + 1 and the columns of a
+// level-m region (its own knots, then the ancestors' knots, then the data):
+//   G = sum over the children of F_c^T F_c (observation-space children, F rows)
+//       or of their Schur blocks (knot-space children);
+//   L L^T = I + G[0:P, 0:P];  Z = G[P:D, 0:P] L^{-T};  S = G[P:D, P:D] - Z Z^T.
+// The parent reads S (lower triangle); prediction reads L^{-1} and Z.
+//
+// k_gram_panel (one workgroup per region): the first block column of G and
+// its last row, the factor and inverse of I + G[0:P, 0:P], Z, and the last
+// row of S (the data row, computed with the vector units).
+// k_gram_tile (one wave per 64 x 64 block of S below the data row): the block
+// is accumulated over all children in registers and written once.
+
+// the children of region g (level m) as runs of consecutive observation-space
+// children (one row range each) and knot-space children (one block each)
+__device__ __forceinline__ bool child_is_rows(const KArgs& a, int m, int64_t gc) {
+    return m + 1 == a.M || a.form[gc] == FOLD_FACTOR;
+}
+
+// y[c] (=|+=) sum_k u(k) v(k, c) for c < N, u(k) = U[k su], v(k, c) = V[k sv + c].
+// Lanes take 64 consecutive columns; the four waves take interleaved slices
+// of 8 rows, each lane keeping 8 independent partial sums so that 16 loads
+// are in flight; the partials are combined in a fixed order (deterministic).
+// red: 4 x 64 doubles of LDS.
+template <bool ADD>
+__device__ __forceinline__ void wg_rowvec(double* y, int N, int K, const double* U, int64_t su, const double* V,
+                                          int64_t sv, double* red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < N; c0 += 64) {
+        const int c = c0 + lane;
+        const bool ok = c < N;
+        double p[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p[u] = 0.0;
+        for (int k = 8 * w; k < K; k += 32) {
+            double uv[8], vv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool kok = k + u < K;
+                uv[u] = ldg0(U, int64_t(k + u) * su, kok);
+                vv[u] = ldg0(V, int64_t(k + u) * sv + c, kok && ok);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) p[u] = fma(uv[u], vv[u], p[u]);
+        }
+        red[w * 64 + lane] = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+        __syncthreads();
+        if (w == 0 && ok) {
+            const double v = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
+            y[c] = ADD ? y[c] + v : v;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(NT, 2) k_gram_panel(KArgs a) {
+    __shared__ Smem s;
+    const int64_t total = a.ntasks * a.ntheta;
+    const int m = a.level, P = a.P, M = a.M;
+    const int cm = (M - 1 - m) * P;
+    const int D = m * P + 1, Dt = D - P;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const int th = int(t / a.ntasks);
+        const int64_t g = a.tasks[t % a.ntasks];
+        const int64_t k = g - a.lvl[m - 1];
+        double* G = a.gram + th * a.gram_stride + a.gram_off[g];
+        const double* Fth = a.F + th * a.F_stride;
+        double* yrow = G + int64_t(D - 1) * D + P;  // last row of S: columns P .. D-1
+        bool first = true;
+        for (int j = 0; j < a.J;) {
+            const int64_t gc = a.lvl[m] + a.J * k + j;
+            if (child_is_rows(a, m, gc)) {
+                // a run of consecutive observation-space children: one row range
+                int j2 = j + 1;
+                while (j2 < a.J && child_is_rows(a, m, a.lvl[m] + a.J * k + j2)) ++j2;
+                const int64_t lo = a.obs_lo[gc], hi = a.obs_hi[a.lvl[m] + a.J * k + j2 - 1];
+                j = j2;
+                const int nc = int(hi - lo);
+                if (nc == 0) continue;
+                const double* Fc = Fth + lo * a.WFs + cm;
+                if (first) {
+                    wg_mm<MM_SET>(G, D, D, P, nc, Fc, 1, a.WFs, Fc, 1, a.WFs, false, s.mm);
+                    wg_rowvec<false>(yrow, Dt, nc, Fc + (D - 1), a.WFs, Fc + P, a.WFs, s.mm);
+                } else {
+                    wg_mm<MM_ADD>(G, D, D, P, nc, Fc, 1, a.WFs, Fc, 1, a.WFs, false, s.mm);
+                    wg_rowvec<true>(yrow, Dt, nc, Fc + (D - 1), a.WFs, Fc + P, a.WFs, s.mm);
+                }
+                first = false;
+            } else {
+                ++j;
+                const double* Gc = a.gram + th * a.gram_stride + a.gram_off[gc];
+                const int Dc = D + P;
+                // panel: G[i][c] for i < D, c < P (lower part of the top block only)
+                for (int64_t e = threadIdx.x; e < int64_t(D) * P; e += NT) {
+                    const int i = int(e / P), c = int(e % P);
+                    if (c <= i) {
+                        const double v = Gc[int64_t(P + i) * Dc + P + c];
+                        G[int64_t(i) * D + c] = first ? v : G[int64_t(i) * D + c] + v;
+                    }
+                }
+                for (int c = threadIdx.x; c < Dt; c += NT) {
+                    const double v = Gc[int64_t(P + D - 1) * Dc + P + P + c];
+                    yrow[c] = first ? v : yrow[c] + v;
+                }
+                __syncthreads();
+                first = false;
+            }
+        }
+        // I + G[0:P, 0:P] -> Cholesky factor and inverse in LDS
+        for (int e = threadIdx.x; e < TB * TB; e += NT) {
+            const int i = e / TB, j = e % TB;
+            s.L[i * MLD + j] = (i < P && j <= i) ? G[int64_t(i) * D + j] + (i == j ? 1.0 : 0.0) : 0.0;
+        }
+        __syncthreads();
+        if (wg_potrf_inv_lds(s.L, P, MLD, s.Li, MLD, &s.flag)) {
+            flag_fail(a, th, g);
+            continue;
+        }
+        if (threadIdx.x == 0) {
+            double ld = 0.0;
+            for (int i = 0; i < P; ++i) ld += log(s.L[i * MLD + i]);
+            a.dval[th * a.d_stride + g] = 2.0 * ld;
+        }
+        for (int e = threadIdx.x; e < P * P; e += NT) {
+            const int i = e / P, j = e % P;
+            G[int64_t(i) * D + j] = (j <= i) ? s.Li[i * MLD + j] : 0.0;
+        }
+        // Z = G[P:D, 0:P] L^{-T} in place
+        double* Z = G + int64_t(P) * D;
+        wg_mm<MM_SET>(Z, D, Dt, P, P, Z, D, 1, s.Li, MLD, 1, false, s.mm);
+        // last row of S: yrow[c] -= Z[Dt-1] . Z[c]; lanes over the P columns
+        // of Z (coalesced rows), one row c per wave step, butterfly sum
+        {
+            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+            const double zy = lane < P ? Z[int64_t(Dt - 1) * D + lane] : 0.0;
+            for (int c = w; c < Dt; c += NT / 64) {
+                double v = lane < P ? zy * Z[int64_t(c) * D + lane] : 0.0;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                if (lane == 0) yrow[c] -= v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One wave per 64 x 64 block (bi >= bj) of S[0:Ds, 0:Ds], Ds = (m-1)P (rows
+// and columns counted from P in G; the data row is done by k_gram_panel).
+// Knot-space children initialise the accumulators, observation-space runs
+// add F_c^T F_c on the matrix cores, Z Z^T is subtracted, and the lower part
+// of the block is written once.
+__global__ void __launch_bounds__(NT, 2) k_gram_tile(KArgs a) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const int m = a.level, P = a.P, M = a.M;
+    const int cm = (M - 1 - m) * P;
+    const int D = m * P + 1, Ds = (m - 1) * P;
+    const int nb = (Ds + TB - 1) / TB;
+    const int64_t ntile = int64_t(nb) * (nb + 1) / 2;
+    const int64_t total = a.ntasks * a.ntheta * ntile;
+    for (int64_t wt = int64_t(blockIdx.x) * 4 + w; wt < total; wt += int64_t(gridDim.x) * 4) {
+        const int64_t rt = wt / ntile;
+        int64_t tix = wt % ntile;
+        int bi = 0;
+        while (tix > bi) { tix -= bi + 1; ++bi; }
+        const int bj = int(tix);
+        const int th = int(rt / a.ntasks);
+        const int64_t g = a.tasks[rt % a.ntasks];
+        const int64_t k = g - a.lvl[m - 1];
+        double* G = a.gram + th * a.gram_stride + a.gram_off[g];
+        const double* Fth = a.F + th * a.F_stride;
+        const int r0 = bi * TB, c0 = bj * TB;  // within S
+        bool rv[4], cv[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            rv[t] = r0 + 16 * t + lr < Ds;
+            cv[t] = c0 + 16 * t + lr < Ds;
+        }
+        v4d acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < a.J;) {
+            const int64_t gc = a.lvl[m] + a.J * k + j;
+            if (child_is_rows(a, m, gc)) {
+                int j2 = j + 1;
+                while (j2 < a.J && child_is_rows(a, m, a.lvl[m] + a.J * k + j2)) ++j2;
+                const int64_t lo = a.obs_lo[gc], hi = a.obs_hi[a.lvl[m] + a.J * k + j2 - 1];
+                j = j2;
+                const int nc = int(hi - lo);
+                if (nc == 0) continue;
+                // S column x is F column cm + P + x
+                const double* Fa = Fth + lo * a.WFs + cm + P + r0;
+                const double* Fb = Fth + lo * a.WFs + cm + P + c0;
+                for (int k0 = 0; k0 < nc; k0 += 16) {
+                    double fa[4][4], fb[4][4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int kk = k0 + 4 * q + lg;
+                        const bool kok = kk < nc;
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int64_t o = int64_t(kk) * a.WFs + 16 * t + lr;
+                            fa[t][q] = ldg0(Fa, o, kok && rv[t]);
+                            fb[t][q] = ldg0(Fb, o, kok && cv[t]);
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int jj = 0; jj < 4; ++jj)
+                                if (bi > bj || jj <= i) acc[i][jj] = mfma(fa[i][q], fb[jj][q], acc[i][jj]);
+                }
+            } else {
+                ++j;  // knot-space child: added in the epilogue
+            }
+        }
+        // - Z Z^T over the P columns of Z (row P + x of G holds Z row x)
+        const double* Za = G + int64_t(P + r0) * D;
+        const double* Zb = G + int64_t(P + c0) * D;
+        for (int k0 = 0; k0 < P; k0 += 16) {
+            double fa[4][4], fb[4][4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int kk = k0 + 4 * q + lg;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    fa[t][q] = ldg0(Za, int64_t(16 * t + lr) * D + kk, rv[t]);
+                    fb[t][q] = ldg0(Zb, int64_t(16 * t + lr) * D + kk, cv[t]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        if (bi > bj || jj <= i) acc[i][jj] = mfma(-fa[i][q], fb[jj][q], acc[i][jj]);
+        }
+        // the lower part of the block, written once (row P + r, column P + c of
+        // G), with the knot-space children's Schur blocks (their rows and
+        // columns P + P + (r, c)) added one 16-row strip at a time
+        const int Dc = D + P;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double add[4][4];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) add[jj][e] = 0.0;
+            for (int j = 0; j < a.J; ++j) {
+                const int64_t gc = a.lvl[m] + a.J * k + j;
+                if (child_is_rows(a, m, gc)) continue;
+                const double* Gc = a.gram + th * a.gram_stride + a.gram_off[gc];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = r0 + 16 * i + lg + 4 * e, c = c0 + 16 * jj + lr;
+                        add[jj][e] += ldg0(Gc, int64_t(2 * P + r) * Dc + 2 * P + c, r < Ds && c < Ds && c <= r);
+                    }
+            }
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = r0 + 16 * i + lg + 4 * e, c = c0 + 16 * jj + lr;
+                    if (r < Ds && c < Ds && c <= r) G[int64_t(P + r) * D + P + c] = acc[i][jj][e] + add[jj][e];
+                }
+        }
+    }
+}
+
+// The same blocks of S, one workgroup per 128 x 128 super-block (bi >= bj):
+// the observation-space rows are staged through LDS 16 at a time, each wave
+// computing one 64 x 64 quarter from the shared copy, so every F row segment
+// is read from memory once per super-block instead of once per 64 x 64 block.
+// The next chunk is loaded into registers while the current one is used.
+constexpr int SB = 128;       // super-block edge
+constexpr int KCH = 16;       // rows per staged chunk
+constexpr int SPAD = SB + 8;  // LDS pitch: the four 16-lane groups of a read fall on different banks
+
+__global__ void __launch_bounds__(NT, 2) k_gram_tile2(KArgs a) {
+    __shared__ double As[KCH * SPAD];
+    __shared__ double Bs[KCH * SPAD];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const int m = a.level, P = a.P, M = a.M;
+    const int cm = (M - 1 - m) * P;
+    const int D = m * P + 1, Ds = (m - 1) * P;
+    const int nsb = (Ds + SB - 1) / SB;
+    const int64_t nst = int64_t(nsb) * (nsb + 1) / 2;
+    const int64_t total = a.ntasks * a.ntheta * nst;
+    const int wr = w >> 1, wc = w & 1;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const int64_t rt = t / nst;
+        int64_t tix = t % nst;
+        int BI = 0;
+        while (tix > BI) { tix -= BI + 1; ++BI; }
+        const int BJ = int(tix);
+        const int th = int(rt / a.ntasks);
+        const int64_t g = a.tasks[rt % a.ntasks];
+        const int64_t k = g - a.lvl[m - 1];
+        double* G = a.gram + th * a.gram_stride + a.gram_off[g];
+        const double* Fth = a.F + th * a.F_stride;
+        const int R0 = BI * SB, C0 = BJ * SB;
+        const int r0 = R0 + 64 * wr, c0 = C0 + 64 * wc;  // this wave's quarter (within S)
+        const bool active = !(BI == BJ && wc > wr);      // quarters above the diagonal are skipped
+        const bool diagq = (BI == BJ && wc == wr);
+        v4d acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < a.J;) {
+            const int64_t gc = a.lvl[m] + a.J * k + j;
+            if (!child_is_rows(a, m, gc)) { ++j; continue; }
+            int j2 = j + 1;
+            while (j2 < a.J && child_is_rows(a, m, a.lvl[m] + a.J * k + j2)) ++j2;
+            const int64_t lo = a.obs_lo[gc], hi = a.obs_hi[a.lvl[m] + a.J * k + j2 - 1];
+            j = j2;
+            const int nc = int(hi - lo);
+            if (nc == 0) continue;
+            const double* base = Fth + lo * a.WFs + cm + P;  // S column x is base[x]
+            // chunk staging: 16 rows x 128 columns per operand, 4 double2 per thread each
+            double2 pa[4], pb[4];
+            auto load_chunk = [&](int k0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int idx = threadIdx.x + NT * q;
+                    const int kr = idx >> 6, c2 = (idx & 63) * 2;
+                    const bool kok = k0 + kr < nc;
+                    const bool aok = kok && R0 + c2 < Ds, bok = kok && C0 + c2 < Ds;
+                    const double* pra = base + int64_t(k0 + kr) * a.WFs + R0 + c2;
+                    const double* prb = base + int64_t(k0 + kr) * a.WFs + C0 + c2;
+                    const double2 va = *reinterpret_cast<const double2*>(aok ? pra : base);
+                    const double2 vb = *reinterpret_cast<const double2*>(bok ? prb : base);
+                    pa[q] = aok ? va : double2{0.0, 0.0};
+                    pb[q] = bok ? vb : double2{0.0, 0.0};
+                }
+            };
+            load_chunk(0);
+            for (int k0 = 0; k0 < nc; k0 += KCH) {
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int idx = threadIdx.x + NT * q;
+                    const int kr = idx >> 6, c2 = (idx & 63) * 2;
+                    *reinterpret_cast<double2*>(As + kr * SPAD + c2) = pa[q];
+                    *reinterpret_cast<double2*>(Bs + kr * SPAD + c2) = pb[q];
+                }
+                __syncthreads();
+                if (k0 + KCH < nc) load_chunk(k0 + KCH);
+                if (active) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int kk = 4 * q + lg;
+                        double fa[4], fb[4];
+#pragma unroll
+                        for (int tt = 0; tt < 4; ++tt) {
+                            fa[tt] = As[kk * SPAD + 64 * wr + 16 * tt + lr];
+                            fb[tt] = Bs[kk * SPAD + 64 * wc + 16 * tt + lr];
+                        }
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int jj = 0; jj < 4; ++jj)
+                                if (!diagq || jj <= i) acc[i][jj] = mfma(fa[i], fb[jj], acc[i][jj]);
+                    }
+                }
+            }
+        }
+        if (active) {
+            bool rv[4], cv[4];
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+                rv[tt] = r0 + 16 * tt + lr < Ds;
+                cv[tt] = c0 + 16 * tt + lr < Ds;
+            }
+            // - Z Z^T over the P columns of Z (row P + x of G holds Z row x)
+            const double* Za = G + int64_t(P + r0) * D;
+            const double* Zb = G + int64_t(P + c0) * D;
+            for (int k0 = 0; k0 < P; k0 += 16) {
+                double fa[4][4], fb[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kk = k0 + 4 * q + lg;
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt) {
+                        fa[tt][q] = ldg0(Za, int64_t(16 * tt + lr) * D + kk, rv[tt]);
+                        fb[tt][q] = ldg0(Zb, int64_t(16 * tt + lr) * D + kk, cv[tt]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj)
+                            if (!diagq || jj <= i) acc[i][jj] = mfma(-fa[i][q], fb[jj][q], acc[i][jj]);
+            }
+            // the lower part of the quarter, written once, knot-space children added
+            const int Dc = D + P;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                double add[4][4];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) add[jj][e] = 0.0;
+                for (int j = 0; j < a.J; ++j) {
+                    const int64_t gc = a.lvl[m] + a.J * k + j;
+                    if (child_is_rows(a, m, gc)) continue;
+                    const double* Gc = a.gram + th * a.gram_stride + a.gram_off[gc];
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int r = r0 + 16 * i + lg + 4 * e, c = c0 + 16 * jj + lr;
+                            add[jj][e] += ldg0(Gc, int64_t(2 * P + r) * Dc + 2 * P + c, r < Ds && c < Ds && c <= r);
+                        }
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = r0 + 16 * i + lg + 4 * e, c = c0 + 16 * jj + lr;
+                        if (r < Ds && c < Ds && c <= r) G[int64_t(P + r) * D + P + c] = acc[i][jj][e] + add[jj][e];
+                    }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// log-likelihood per theta: -1/2 [ n log 2 pi + sum of log-determinants + q ],
+// q the quadratic form left in the root's statistics.  Fixed-order sums.
+__global__ void __launch_bounds__(NT) k_final(KArgs a, int64_t nreg, int root_gram) {
+    __shared__ double red[NT];
+    const int th = blockIdx.x;
+    const double* d = a.dval + th * a.d_stride;
+    double sd = 0.0;
+    for (int64_t g = threadIdx.x; g < nreg; g += NT) sd += d[g];
+    red[threadIdx.x] = sd;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w /= 2) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double dsum = red[0];
+    __syncthreads();
+    double q = 0.0;
+    if (root_gram) {
+        const int D = a.P + 1;
+        q = a.gram[th * a.gram_stride + a.gram_off[0] + int64_t(a.P) * D + a.P];
+    } else {
+        const double* F = a.F + th * a.F_stride;
+        const int64_t n = int64_t(a.n_used);
+        double sq = 0.0;
+        for (int64_t r = threadIdx.x; r < n; r += NT) {
+            const double y = F[r * a.WFs + (a.WF - 1)];
+            sq = fma(y, y, sq);
+        }
+        red[threadIdx.x] = sq;
+        __syncthreads();
+        for (int w = NT / 2; w > 0; w /= 2) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        q = red[0];
+    }
+    if (threadIdx.x == 0) {
+        const double LOG2PI = 1.8378770664093454835606594728112;
+        double ll = -0.5 * (a.n_used * LOG2PI + dsum + q);
+        const double* thp = a.theta + 3 * th;
+        const bool ok = thp[0] > 0.0 && thp[1] > 0.0 && (thp[2] > 0.0 || (a.zero_nugget && thp[2] == 0.0)) &&
+                        thp[0] < 1.0 / 0.0 && thp[1] < 1.0 / 0.0 && thp[2] < 1.0 / 0.0;
+        const bool bad = a.status[th] != 0 || !ok;
+        if (bad) ll = __builtin_nan("");
+        a.out[th] = ll;
+        if (a.out_ld) a.out_ld[th] = bad ? __builtin_nan("") : dsum;
+        if (a.out_q) a.out_q[th] = bad ? __builtin_nan("") : q;
+    }
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_int(int* p, int64_t n, int v) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+// ---- host-side launchers
+
+hipError_t launch_gram_panel(const KArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_gram_panel, dim3(grid), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_gram_tile2(const KArgs& a, hipStream_t st) {
+    const int Ds = (a.level - 1) * a.P;
+    const int64_t nsb = (Ds + SB - 1) / SB;
+    const int64_t blocks = std::min<int64_t>(a.ntasks * a.ntheta * nsb * (nsb + 1) / 2, int64_t(1) << 20);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gram_tile2, dim3(unsigned(blocks)), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_gram_tile(const KArgs& a, hipStream_t st) {
+    const int Ds = (a.level - 1) * a.P;
+    const int64_t nb = (Ds + TB - 1) / TB;
+    const int64_t waves = a.ntasks * a.ntheta * nb * (nb + 1) / 2;
+    if (waves == 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((waves + 3) / 4, int64_t(1) << 20);
+    hipLaunchKernelGGL(k_gram_tile, dim3(unsigned(blocks)), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+hipError_t launch_final(const KArgs& a, int64_t nreg, int root_gram, hipStream_t st) {
+    hipLaunchKernelGGL(k_final, dim3(a.ntheta), dim3(NT), 0, st, a, nreg, root_gram);
+    return hipGetLastError();
+}
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill, dim3(unsigned(blocks < 4096 ? blocks : 4096)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_int, dim3(unsigned(blocks < 4096 ? blocks : 4096)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace mra
