@@ -292,8 +292,8 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
                 else if (np <= 64 && np <= smax) t.fsmall_tasks[2][m].push_back(int(g));
                 else {
                     t.factor_tasks[m].push_back(int(g));
-                    // the matrix and the inverses of its 64 x 64 diagonal blocks
-                    t.scratch_fold = std::max(t.scratch_fold, np * np + ((np + 63) / 64) * 4096);
+                    // the matrix, rows padded to a multiple of 4
+                    t.scratch_fold = std::max(t.scratch_fold, np * ((np + 3) & ~int64_t(3)));
                 }
             } else {
                 t.gram_tasks[m].push_back(int(g));
@@ -312,7 +312,7 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
         const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
         if (nc > smax) {
             t.leaf_tasks.push_back(int(g));
-            t.scratch_leaf = std::max(t.scratch_leaf, nc * nc + ((nc + 63) / 64) * 4096);
+            t.scratch_leaf = std::max(t.scratch_leaf, nc * ((nc + 3) & ~int64_t(3)));
         } else if (nc > 32) {
             t.small_tasks[2].push_back(int(g));
         } else if (nc > 16) {
@@ -738,7 +738,7 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
     const Plan& pl = t->lik;
     const int64_t F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
     const int64_t per_theta = pl.vst_size + F_stride + pl.gram_size + h.nreg;
-    const int64_t scratch_per = std::max<int64_t>({pl.scratch_leaf, pl.scratch_fold, 1});
+    const int64_t scratch_per = (std::max<int64_t>({pl.scratch_leaf, pl.scratch_fold, 1}) + 31) & ~int64_t(31);
     // reuse when the buffers hold enough theta per chunk (or could not hold more)
     if (w.Bc > 0 && w.cap_B >= B && (w.Bc >= B || w.mem_limited)) return MRA_OK;
     if (w.Bc > 0) w.release();
@@ -1189,7 +1189,8 @@ extern "C" int mra_predict(const mra_tree* t, int family, double nu, const doubl
     }
     // device buffers (one theta)
     const int64_t F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
-    const int64_t scratch_per = std::max<int64_t>({pl.scratch_leaf, pl.scratch_fold, nmax * nmax + nmax * (t->WFs + kmax), 1});
+    const int64_t scratch_per =
+        (std::max<int64_t>({pl.scratch_leaf, pl.scratch_fold, nmax * nmax + nmax * (t->WFs + kmax), 1}) + 31) & ~int64_t(31);
     const int64_t nslot = 256;
     double *d_th = nullptr, *vst = nullptr, *F = nullptr, *gram = nullptr, *dval = nullptr, *scratch = nullptr,
            *PV = nullptr, *PS = nullptr, *PVAR = nullptr, *d_px = nullptr, *d_py = nullptr, *d_mean = nullptr,

@@ -301,6 +301,132 @@ __device__ __forceinline__ bool wg_potrf_inv_lds(double* T, int n, int ld, doubl
     return bad;
 }
 
+// Cholesky factor and its inverse of an n x n (n <= 64) lower triangle held
+// in a 64 x 64 LDS tile T (pitch ld), by one wave, with no workgroup barrier:
+// on return T holds L^{-1} (lower, zeros above the diagonal, identity beyond
+// n) where L L^T is the input, and *logdet = sum log diag L.  Returns true
+// (uniformly) when a pivot is not positive.
+// The tile is processed in 16 x 16 blocks, right-looking: each diagonal block
+// is factored in registers (lane r of every 16-lane group holds row r; the
+// column of the factor is broadcast with lane reads) and inverted by forward
+// substitution with broadcast LDS reads; the panel below it is multiplied by
+// that inverse and the trailing blocks are updated on the matrix cores.  The
+// off-diagonal blocks of L^{-1} then follow block row by block row:
+// X_ij = -D_i^{-1} sum_{k=j}^{i-1} L_ik X_kj with D_i^{-1} the diagonal
+// inverses.
+__device__ __forceinline__ bool wave_chol_inv64(double* T, int ld, int n, double* logdet) {
+    const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+    // identity beyond n (rows and columns), so that padding factors to itself
+    for (int e = lane; e < 64 * 64; e += 64) {
+        const int i = e >> 6, j = e & 63;
+        if ((i >= n || j >= n) && j <= i) T[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    }
+    wsync();
+    bool bad = false;
+    double lsum = 0.0;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        double* Dg = T + 16 * kb * ld + 16 * kb;
+        // (1) factor the 16 x 16 diagonal block; lane r (r = lr) keeps row r
+        double d[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) d[k] = (k <= lr) ? Dg[lr * ld + k] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const double piv = bcast(d[j], j);
+            bad = bad || !(piv > 0.0);
+            const double sd = sqrt(piv > 0.0 ? piv : 1.0);
+            lsum += log(sd);
+            const double rs = 1.0 / sd;
+            const double lij = (lr > j) ? d[j] * rs : (lr == j ? sd : 0.0);
+            d[j] = lij;
+#pragma unroll
+            for (int k = j + 1; k < 16; ++k) d[k] = fma(-lij, bcast(lij, k), d[k]);
+        }
+        wsync();
+        if (lg == 0) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k <= lr) Dg[lr * ld + k] = d[k];
+        }
+        wsync();
+        // (2) its inverse: lane c computes column c by forward substitution
+        double x[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            double acc = (q == lr) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < q; ++k) acc = fma(-Dg[q * ld + k], x[k], acc);
+            x[q] = (q >= lr) ? acc / Dg[q * ld + q] : 0.0;
+        }
+        wsync();
+        if (lg == 0) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) Dg[q * ld + lr] = x[q];  // zeros above the diagonal
+        }
+        wsync();
+        // (3) panel: L_ib = A_ib D^{-T} for the blocks below
+#pragma unroll
+        for (int ib = kb + 1; ib < 4; ++ib) {
+            v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc = mfma(T[(16 * ib + lr) * ld + 16 * kb + 4 * q + lg], Dg[lr * ld + 4 * q + lg], acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) T[(16 * ib + lg + 4 * i) * ld + 16 * kb + lr] = acc[i];
+        }
+        wsync();
+        // (4) trailing blocks: A_ij -= L_ik L_jk^T
+#pragma unroll
+        for (int jb = kb + 1; jb < 4; ++jb)
+#pragma unroll
+            for (int ib = jb; ib < 4; ++ib) {
+                v4d acc;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[i] = T[(16 * ib + lg + 4 * i) * ld + 16 * jb + lr];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc = mfma(-T[(16 * ib + lr) * ld + 16 * kb + 4 * q + lg], T[(16 * jb + lr) * ld + 16 * kb + 4 * q + lg],
+                               acc);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) T[(16 * ib + lg + 4 * i) * ld + 16 * jb + lr] = acc[i];
+            }
+        wsync();
+    }
+    // (5) off-diagonal blocks of L^{-1}, block row by block row
+#pragma unroll
+    for (int ib = 1; ib < 4; ++ib) {
+        v4d out[3];
+#pragma unroll
+        for (int jb = 0; jb < ib; ++jb) {
+            v4d y = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = jb; k < ib; ++k)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    y = mfma(T[(16 * ib + lr) * ld + 16 * k + 4 * q + lg], T[(16 * k + 4 * q + lg) * ld + 16 * jb + lr], y);
+            v4d z = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) z = mfma(-T[(16 * ib + lr) * ld + 16 * ib + 4 * e + lg], y[e], z);
+            out[jb] = z;
+        }
+        wsync();
+#pragma unroll
+        for (int jb = 0; jb < ib; ++jb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) T[(16 * ib + lg + 4 * i) * ld + 16 * jb + lr] = out[jb][i];
+        wsync();
+    }
+    // zeros above the diagonal blocks
+    for (int e = lane; e < 64 * 64; e += 64) {
+        const int i = e >> 6, j = e & 63;
+        if ((j >> 4) > (i >> 4)) T[i * ld + j] = 0.0;
+    }
+    wsync();
+    *logdet = lsum;
+    return bad;
+}
+
 // Load an n x n lower triangle (generic pointer, ldg) into LDS (ld), zero
 // elsewhere in the 64 x 64 tile.  All loads of a thread are issued first.
 __device__ __forceinline__ void load_tile(double* T, int ld, const double* G, int64_t ldg, int n) {

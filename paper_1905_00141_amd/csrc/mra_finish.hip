@@ -224,92 +224,307 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 2 : 1)) k_small(KArgs a) {
     }
 }
 
-// Finest-level regions: S = C(S,S) - sum_l V^l V^l^T + tau I, its Cholesky
-// factor, d = log det S, and F <- L_S^{-1} [V^{M-1} .. V^1 | z] in place.
-// S lives in the workgroup's global scratch slot (n^2 doubles).
-__global__ void __launch_bounds__(NT) k_leaf_finish(KArgs a) {
-    __shared__ Smem s;
+// Workgroup finisher for regions of more than 64 rows (one workgroup per
+// region and theta, grid-stride over tasks):
+//   FIN_LEAF (finest level): A = C(S,S) + tau I - V V^T, V the rows' F
+//     columns [0, (M-1)P); right-hand sides X = all WF columns (z copied into
+//     the last one first).
+//   FIN_FOLD (observation-space fold at a.level): A = I + F_m F_m^T, F_m the
+//     columns of the region's own knots; X = the columns after them.
+// Then A = L L^T, d = log det A and X <- L^{-1} X in place.  A (n x n lower,
+// row pitch n rounded up to 4) lives in the workgroup's global scratch slot.
+// Blocked right-looking Cholesky with 64-wide block columns: the diagonal
+// block is factored and inverted by one wave in LDS (wave_chol_inv64); the
+// right-hand sides of the block rows are solved with that inverse (each wave
+// a 16-column slice at a time, the slice in registers); the panel below is
+// formed 64 rows at a time as A_ik L_kk^{-T} in LDS, then the trailing
+// triangle and the right-hand sides of those rows are updated with it.  Every
+// matrix product runs on the matrix cores; the k index of a 16-wide step is
+// permuted the same way on both operands (lane group g holds k = 4g .. 4g+3),
+// so that F rows are loaded four consecutive doubles at a time.
+constexpr int FPD = 65;  // LDS pitch of the 64-column tiles
+
+template <int MODE>
+__device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn, double* red, int* flag) {
+    const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
     const int64_t total = a.ntasks * a.ntheta;
-    const int M = a.M;
-    double* Sg = a.scratch + blockIdx.x * a.scratch_stride;
+    const int M = a.M, P = a.P;
+    const int cm = MODE == FIN_LEAF ? 0 : (M - 1 - a.level) * P;  // first product column
+    const int K = MODE == FIN_LEAF ? (M - 1) * P : P;             // product columns
+    const int xc0 = MODE == FIN_LEAF ? 0 : cm + P;                 // first right-hand-side column
+    const int W = a.WF - xc0;                                      // right-hand-side columns
+    const int nsl = (W + 15) / 16;                                 // 16-column slices
+    double* Ag = a.scratch + int64_t(blockIdx.x) * a.scratch_stride;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         const int th = int(t / a.ntasks);
         const int64_t g = a.tasks[t % a.ntasks];
         const int64_t lo = a.obs_lo[g];
         const int n = int(a.obs_hi[g] - lo);
+        const int lda = (n + 3) & ~3;
         const double* thp = a.theta + 3 * th;
         const double alpha = thp[0], inv_beta = 1.0 / thp[1], tau = thp[2];
-        double* Frows = a.F + th * a.F_stride + lo * a.WFs;
+        double* Fr = a.F + th * a.F_stride + lo * a.WFs;
         const double* px = a.x + lo;
         const double* py = a.y + lo;
-        double* S = Sg;
-        const int64_t lds = n;
-        for (int r = threadIdx.x; r < n; r += NT) Frows[int64_t(r) * a.WFs + (a.WF - 1)] = a.z[lo + r];
-        for (int64_t e0 = 0; e0 < int64_t(n) * n; e0 += 4 * NT) {
-            double xi[4], yi[4], xj[4], yj[4];
+        if (MODE == FIN_LEAF)
+            for (int r = tid; r < n; r += NT) Fr[int64_t(r) * a.WFs + (a.WF - 1)] = a.z[lo + r];
+        // ---- 1. the matrix: 16-row strips (round robin over the waves),
+        // 64 columns (four 16 x 16 tiles) at a time, lower triangle
+        const int ns = (n + 15) / 16;
+        for (int st = ns - 1 - w; st >= 0; st -= 4) {
+            const int r = 16 * st + lr;
+            const bool rok = r < n;
+            const double* ra = Fr + (rok ? int64_t(r) * a.WFs : 0) + cm;
+            for (int cg = 0; cg <= st; cg += 4) {
+                v4d acc[4];
 #pragma unroll
-            for (int j2 = 0; j2 < 4; ++j2) {
-                const int64_t e = e0 + threadIdx.x + j2 * NT;
-                const bool ok = e < int64_t(n) * n;
-                const int i = ok ? int(e / n) : 0, j = ok ? int(e % n) : 0;
-                xi[j2] = px[i]; yi[j2] = py[i]; xj[j2] = px[j]; yj[j2] = py[j];
-            }
+                for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+                const double* cb[4];
+                bool cok[4];
 #pragma unroll
-            for (int j2 = 0; j2 < 4; ++j2) {
-                const int64_t e = e0 + threadIdx.x + j2 * NT;
-                const int i = int(e / n), j = int(e % n);
-                if (e < int64_t(n) * n && j <= i) {
-                    double v = cov_pts(xi[j2], yi[j2], xj[j2], yj[j2], alpha, inv_beta, a.smooth);
-                    if (i == j) v += tau;
-                    S[i * lds + j] = v;
+                for (int c = 0; c < 4; ++c) {
+                    const int cc = 16 * (cg + c) + lr;
+                    cok[c] = cg + c <= st && cc < n;
+                    cb[c] = Fr + (cok[c] ? int64_t(cc) * a.WFs : 0) + cm;
+                }
+                for (int k0 = 0; k0 < K; k0 += 32) {
+                    v4d av[2], bv[2][4];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int kk = k0 + 16 * h + 4 * lg;
+                        av[h] = (rok && kk < K) ? *reinterpret_cast<const v4d*>(ra + kk) : v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            bv[h][c] = (cok[c] && kk < K) ? *reinterpret_cast<const v4d*>(cb[c] + kk)
+                                                          : v4d{0.0, 0.0, 0.0, 0.0};
+                    }
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) acc[c] = mfma(av[h][j], bv[h][c][j], acc[c]);
+                }
+                // epilogue: lane holds column 16 (cg + c) + lr of rows 16 st + lg + 4 i
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int cc = 16 * (cg + c) + lr;
+                    if (cg + c > st || cc >= n) continue;
+                    double cx = 0.0, cy = 0.0;
+                    if (MODE == FIN_LEAF) { cx = px[cc]; cy = py[cc]; }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int rr = 16 * st + lg + 4 * i;
+                        if (rr < n && cc <= rr) {
+                            double v;
+                            if (MODE == FIN_LEAF) {
+                                v = cov_pts(px[rr], py[rr], cx, cy, alpha, inv_beta, a.smooth) - acc[c][i];
+                                if (rr == cc) v += tau;
+                            } else {
+                                v = acc[c][i] + (rr == cc ? 1.0 : 0.0);
+                            }
+                            Ag[int64_t(rr) * lda + cc] = v;
+                        }
+                    }
                 }
             }
         }
         __syncthreads();
-        if (M > 1) wg_mm<MM_SUB>(S, lds, n, n, (M - 1) * a.P, Frows, a.WFs, 1, Frows, a.WFs, 1, true, s.mm);
+        // ---- 2. blocked factorization and solve
         double logdet = 0.0;
-        double* Lst = S + int64_t(n) * n;  // inverses of the diagonal blocks
-        if (wg_potrf(S, lds, n, s.L, s.Li, s.mm, &s.flag, &logdet, Lst)) {
+        bool failed = false;
+        for (int j0 = 0; j0 < n; j0 += 64) {
+            const int jb = min(64, n - j0);
+            // a. the diagonal block into LDS (lower part)
+            for (int e = tid; e < 64 * 64; e += NT) {
+                const int i = e >> 6, j = e & 63;
+                Tt[i * FPD + j] = (i < jb && j <= i) ? Ag[int64_t(j0 + i) * lda + j0 + j] : 0.0;
+            }
+            __syncthreads();
+            // b. one wave: factor and inverse
+            if (w == 0) {
+                double ldv = 0.0;
+                const bool bad = wave_chol_inv64(Tt, FPD, jb, &ldv);
+                if (lane == 0) { *flag = bad ? 1 : 0; red[0] = ldv; }
+            }
+            __syncthreads();
+            if (*flag) { failed = true; break; }
+            logdet += red[0];
+            // c. right-hand sides of the block rows: X_k <- L_kk^{-1} X_k
+            for (int sl = w; sl < nsl; sl += 4) {
+                const int c = xc0 + 16 * sl + lr;
+                const bool cok = c < a.WF;
+                v4d xv[4];
+#pragma unroll
+                for (int t2 = 0; t2 < 4; ++t2)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int rr = 16 * t2 + lg + 4 * i;
+                        xv[t2][i] = ldg0(Fr, int64_t(j0 + rr) * a.WFs + c, cok && rr < jb);
+                    }
+#pragma unroll
+                for (int t2 = 0; t2 < 4; ++t2) {
+                    if (16 * t2 >= jb) break;
+                    v4d o = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int k2 = 0; k2 <= t2; ++k2)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            o = mfma(Tt[(16 * t2 + lr) * FPD + 16 * k2 + 4 * q + lg], xv[k2][q], o);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int rr = 16 * t2 + lg + 4 * i;
+                        if (cok && rr < jb) Fr[int64_t(j0 + rr) * a.WFs + c] = o[i];
+                    }
+                }
+            }
+            __syncthreads();
+            // d. the panel below, 64 rows at a time
+            for (int r0 = j0 + 64; r0 < n; r0 += 64) {
+                // i. P = A[r0 .., j0 ..] L_kk^{-T}: wave w forms rows r0 + 16 w .. + 15
+                {
+                    const int r = r0 + 16 * w + lr;
+                    const bool rok = r < n;
+                    const double* ra = Ag + (rok ? int64_t(r) * lda : 0) + j0;
+                    v4d acc[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const int k = 16 * kk + 4 * lg;
+                        double av[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) av[j] = (rok && k + j < jb) ? ra[k + j] : 0.0;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) acc[c] = mfma(av[j], Tt[(16 * c + lr) * FPD + k + j], acc[c]);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int rr = 16 * w + lg + 4 * i, cc = 16 * c + lr;
+                            Pn[rr * FPD + cc] = acc[c][i];
+                            if (r0 + rr < n) Ag[int64_t(r0 + rr) * lda + j0 + cc] = acc[c][i];
+                        }
+                }
+                __syncthreads();
+                // ii. trailing triangle of these rows: A[r][c] -= P_r . P_c for
+                // j0 + 64 <= c <= r (P_c from LDS for this chunk, from the
+                // scratch slot for earlier chunks)
+                {
+                    const int R = r0 + 16 * w;
+                    if (R < n) {
+                        for (int cb0 = j0 + 64; cb0 <= r0; cb0 += 64) {
+                            const bool here = cb0 == r0;
+                            v4d acc[4];
+                            bool tok[4];
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                const int c0 = cb0 + 16 * c;
+                                tok[c] = c0 < n && c0 <= R + 15;
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) {
+                                    const int rr = R + lg + 4 * i, cc = c0 + lr;
+                                    acc[c][i] = ldg0(Ag, int64_t(rr) * lda + cc, tok[c] && rr < n && cc < n && cc <= rr);
+                                }
+                            }
+#pragma unroll
+                            for (int kk = 0; kk < 4; ++kk) {
+                                const int k = 16 * kk + 4 * lg;
+                                double av[4], bv[4][4];
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) av[j] = Pn[(16 * w + lr) * FPD + k + j];
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) {
+                                    const int cr = 16 * c + lr;  // row of P within its chunk
+                                    if (here) {
+#pragma unroll
+                                        for (int j = 0; j < 4; ++j) bv[c][j] = Pn[cr * FPD + k + j];
+                                    } else {
+                                        const bool ok = tok[c] && cb0 + cr < n;
+                                        const v4d v = *reinterpret_cast<const v4d*>(Ag + (ok ? int64_t(cb0 + cr) * lda + j0 + k : 0));
+#pragma unroll
+                                        for (int j = 0; j < 4; ++j) bv[c][j] = ok ? v[j] : 0.0;
+                                    }
+                                }
+#pragma unroll
+                                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                                    for (int c = 0; c < 4; ++c) acc[c] = mfma(-av[j], bv[c][j], acc[c]);
+                            }
+#pragma unroll
+                            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) {
+                                    const int rr = R + lg + 4 * i, cc = cb0 + 16 * c + lr;
+                                    if (tok[c] && rr < n && cc < n && cc <= rr) Ag[int64_t(rr) * lda + cc] = acc[c][i];
+                                }
+                        }
+                    }
+                }
+                // iii. right-hand sides of these rows: X_r -= P_r X_k
+                for (int sl = w; sl < nsl; sl += 4) {
+                    const int c = xc0 + 16 * sl + lr;
+                    const bool cok = c < a.WF;
+                    double xb[4][4];  // X_k[16 kk + 4 lg + j][c]
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int k = 16 * kk + 4 * lg + j;
+                            xb[kk][j] = ldg0(Fr, int64_t(j0 + k) * a.WFs + c, cok && k < jb);
+                        }
+#pragma unroll
+                    for (int rt = 0; rt < 4; ++rt) {
+                        if (r0 + 16 * rt >= n) break;
+                        v4d o;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int rr = r0 + 16 * rt + lg + 4 * i;
+                            o[i] = ldg0(Fr, int64_t(rr) * a.WFs + c, cok && rr < n);
+                        }
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                            for (int j = 0; j < 4; ++j)
+                                o = mfma(-Pn[(16 * rt + lr) * FPD + 16 * kk + 4 * lg + j], xb[kk][j], o);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int rr = r0 + 16 * rt + lg + 4 * i;
+                            if (cok && rr < n) Fr[int64_t(rr) * a.WFs + c] = o[i];
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (failed) {
             flag_fail(a, th, g);
+            __syncthreads();
             continue;
         }
-        if (threadIdx.x == 0) a.dval[th * a.d_stride + g] = 2.0 * logdet;
-        wg_trsm_lln(S, lds, n, Frows, a.WFs, a.WF, s.L, s.Li, s.mm, &s.flag, true, Lst);
+        if (tid == 0) a.dval[th * a.d_stride + g] = 2.0 * logdet;
+        __syncthreads();
     }
 }
 
-// Fold in observation space for regions at `level` whose subtree holds few
-// observations: G = I + F_m F_m^T over the region's rows (F_m: the columns of
-// this region's own knots), d = log det G, and F_rest <- L_G^{-1} F_rest.
+__global__ void __launch_bounds__(NT, 2) k_leaf_finish(KArgs a) {
+    __shared__ double Tt[64 * FPD];
+    __shared__ double Pn[64 * FPD];
+    __shared__ double red[4];
+    __shared__ int flag;
+    fin_body<FIN_LEAF>(a, Tt, Pn, red, &flag);
+}
+
 __global__ void __launch_bounds__(NT, 2) k_fold_factor(KArgs a) {
-    __shared__ Smem s;
-    const int64_t total = a.ntasks * a.ntheta;
-    const int m = a.level, P = a.P;
-    const int cm = (a.M - 1 - m) * P;
-    double* Gg = a.scratch + blockIdx.x * a.scratch_stride;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const int th = int(t / a.ntasks);
-        const int64_t g = a.tasks[t % a.ntasks];
-        const int64_t lo = a.obs_lo[g];
-        const int n = int(a.obs_hi[g] - lo);
-        double* Frows = a.F + th * a.F_stride + lo * a.WFs;
-        double* G = Gg;
-        const int64_t ldg = n;
-        for (int64_t e = threadIdx.x; e < int64_t(n) * n; e += NT) {
-            const int i = int(e / n), j = int(e % n);
-            if (j <= i) G[i * ldg + j] = (i == j) ? 1.0 : 0.0;
-        }
-        __syncthreads();
-        wg_mm<MM_ADD>(G, ldg, n, n, P, Frows + cm, a.WFs, 1, Frows + cm, a.WFs, 1, true, s.mm);
-        double logdet = 0.0;
-        double* Lst = G + int64_t(n) * n;  // inverses of the diagonal blocks
-        if (wg_potrf(G, ldg, n, s.L, s.Li, s.mm, &s.flag, &logdet, Lst)) {
-            flag_fail(a, th, g);
-            continue;
-        }
-        if (threadIdx.x == 0) a.dval[th * a.d_stride + g] = 2.0 * logdet;
-        wg_trsm_lln(G, ldg, n, Frows + cm + P, a.WFs, a.WF - cm - P, s.L, s.Li, s.mm, &s.flag, true, Lst);
-    }
+    __shared__ double Tt[64 * FPD];
+    __shared__ double Pn[64 * FPD];
+    __shared__ double red[4];
+    __shared__ int flag;
+    fin_body<FIN_FOLD>(a, Tt, Pn, red, &flag);
 }
 
 // ---- host-side launchers

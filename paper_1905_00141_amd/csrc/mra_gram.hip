@@ -117,22 +117,28 @@ __global__ void __launch_bounds__(NT, 2) k_gram_panel(KArgs a) {
             s.L[i * MLD + j] = (i < P && j <= i) ? G[int64_t(i) * D + j] + (i == j ? 1.0 : 0.0) : 0.0;
         }
         __syncthreads();
-        if (wg_potrf_inv_lds(s.L, P, MLD, s.Li, MLD, &s.flag)) {
+        // one wave: the factor's inverse replaces the tile
+        if ((threadIdx.x >> 6) == 0) {
+            double ldv = 0.0;
+            const bool bad = wave_chol_inv64(s.L, MLD, P, &ldv);
+            if (threadIdx.x == 0) { s.flag = bad ? 1 : 0; s.Li[0] = ldv; }
+        }
+        __syncthreads();
+        const bool bad = s.flag != 0;
+        const double ldv = s.Li[0];
+        __syncthreads();
+        if (bad) {
             flag_fail(a, th, g);
             continue;
         }
-        if (threadIdx.x == 0) {
-            double ld = 0.0;
-            for (int i = 0; i < P; ++i) ld += log(s.L[i * MLD + i]);
-            a.dval[th * a.d_stride + g] = 2.0 * ld;
-        }
+        if (threadIdx.x == 0) a.dval[th * a.d_stride + g] = 2.0 * ldv;
         for (int e = threadIdx.x; e < P * P; e += NT) {
             const int i = e / P, j = e % P;
-            G[int64_t(i) * D + j] = (j <= i) ? s.Li[i * MLD + j] : 0.0;
+            G[int64_t(i) * D + j] = (j <= i) ? s.L[i * MLD + j] : 0.0;
         }
         // Z = G[P:D, 0:P] L^{-T} in place
         double* Z = G + int64_t(P) * D;
-        wg_mm<MM_SET>(Z, D, Dt, P, P, Z, D, 1, s.Li, MLD, 1, false, s.mm);
+        wg_mm<MM_SET>(Z, D, Dt, P, P, Z, D, 1, s.L, MLD, 1, false, s.mm);
         // last row of S: yrow[c] -= Z[Dt-1] . Z[c]; lanes over the P columns
         // of Z (coalesced rows), one row c per wave step, butterfly sum
         {
