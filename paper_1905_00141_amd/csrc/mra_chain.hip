@@ -17,9 +17,11 @@ namespace mra {
 // operand: the summation index is permuted consistently on the A operand,
 // which is staged in LDS one P x P block at a time.
 // Staging of a P x P block (row-major, ld; rows 16-byte aligned) into LDS,
-// transposed with an odd pitch: blk[c * (P + 1) + r] = src[r][c], so that the
-// 16 lanes of a group, which read 16 consecutive rows r of one column c, hit
-// 16 different banks.  Split in two for software pipelining: the loads of the
+// row-major with pitch P + 2: blk[r * (P + 2) + c] = src[r][c].  A matrix-core
+// operand read (lane (l, g) of a 16-lane group reads row r0 + l, column
+// c0 + g) then touches every one of the 64 four-byte banks exactly twice (the
+// minimum for 64 lanes of 8 bytes), and the staging stores of consecutive
+// lanes are consecutive.  Split in two for software pipelining: the loads of the
 // next block (into registers) are issued before the current block is used, so
 // their latency overlaps the matrix-core work; the stores into LDS follow.
 template <int P>
@@ -47,8 +49,8 @@ __device__ __forceinline__ void stage_store(double* blk, const StageRegs<P>& rg)
         const int e = threadIdx.x + j * NT;
         if (e < E2) {
             const int r = (2 * e) / P, c = (2 * e) % P;
-            blk[c * (P + 1) + r] = rg.v[j].x;
-            blk[(c + 1) * (P + 1) + r] = rg.v[j].y;
+            blk[r * (P + 2) + c] = rg.v[j].x;
+            blk[r * (P + 2) + c + 1] = rg.v[j].y;
         }
     }
 }
@@ -59,7 +61,7 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
     constexpr int GS = 128 / P;  // accumulator budget for two workgroups per CU
     // two staging buffers: block s is written while block s - 1 may still be
     // read, so one barrier per block suffices
-    __shared__ double blk2[2][P * (P + 1)];
+    __shared__ __align__(16) double blk2[2][P * (P + 2)];
     // the ancestors' knot bars (a knot is a pair of bars, r_hat <= 64 gives <= 8 each)
     __shared__ double kbx[MAXL * 8], kby[MAXL * 8];
     __shared__ int kq[P];  // knot q -> its bars: (q % nx) + 8 (q / nx), or -1 beyond r_hat
@@ -190,7 +192,7 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
                                     const double bv = vi[mt2][q];
 #pragma unroll
                                     for (int mt = 0; mt < NM; ++mt)
-                                        acc[l][mt] = mfma(-blk[(16 * mt2 + lg + 4 * q) * (P + 1) + 16 * mt + lr], bv, acc[l][mt]);
+                                        acc[l][mt] = mfma(-blk[(16 * mt + lr) * (P + 2) + 16 * mt2 + lg + 4 * q], bv, acc[l][mt]);
                                 }
                         }
                     }
@@ -210,7 +212,7 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
                                 for (int mt2 = 0; mt2 <= mt; ++mt2)
 #pragma unroll
                                     for (int q = 0; q < 4; ++q)
-                                        vn = mfma(blk[(16 * mt2 + lg + 4 * q) * (P + 1) + 16 * mt + lr], acc[i][mt2][q], vn);
+                                        vn = mfma(blk[(16 * mt + lr) * (P + 2) + 16 * mt2 + lg + 4 * q], acc[i][mt2][q], vn);
                                 vi[mt] = vn;
                             }
                             if (store) {
@@ -233,7 +235,7 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
                                         const double bv = vi[mt2][q];
 #pragma unroll
                                         for (int mt = 0; mt < NM; ++mt)
-                                            acc[l][mt] = mfma(-blk[(16 * mt2 + lg + 4 * q) * (P + 1) + 16 * mt + lr], bv, acc[l][mt]);
+                                            acc[l][mt] = mfma(-blk[(16 * mt + lr) * (P + 2) + 16 * mt2 + lg + 4 * q], bv, acc[l][mt]);
                                     }
                             }
                         }

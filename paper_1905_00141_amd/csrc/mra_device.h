@@ -301,8 +301,8 @@ __device__ __forceinline__ bool wg_potrf_inv_lds(double* T, int n, int ld, doubl
     return bad;
 }
 
-// Cholesky factor and its inverse of an n x n (n <= 64) lower triangle held
-// in a 64 x 64 LDS tile T (pitch ld), by one wave, with no workgroup barrier:
+// Cholesky factor and its inverse of an n x n (n <= 16 NB) lower triangle held
+// in a 16 NB x 16 NB LDS tile T (pitch ld), by one wave, with no workgroup barrier:
 // on return T holds L^{-1} (lower, zeros above the diagonal, identity beyond
 // n) where L L^T is the input, and *logdet = sum log diag L.  Returns true
 // (uniformly) when a pivot is not positive.
@@ -314,29 +314,37 @@ __device__ __forceinline__ bool wg_potrf_inv_lds(double* T, int n, int ld, doubl
 // off-diagonal blocks of L^{-1} then follow block row by block row:
 // X_ij = -D_i^{-1} sum_{k=j}^{i-1} L_ik X_kj with D_i^{-1} the diagonal
 // inverses.
-__device__ __forceinline__ bool wave_chol_inv64(double* T, int ld, int n, double* logdet) {
+template <int NB>
+__device__ __forceinline__ bool wave_chol_inv(double* T, int ld, int n, double* logdet) {
+    constexpr int NT16 = 16 * NB;
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
     // identity beyond n (rows and columns), so that padding factors to itself
-    for (int e = lane; e < 64 * 64; e += 64) {
-        const int i = e >> 6, j = e & 63;
+    for (int e = lane; e < NT16 * NT16; e += 64) {
+        const int i = e / NT16, j = e % NT16;
         if ((i >= n || j >= n) && j <= i) T[i * ld + j] = (i == j) ? 1.0 : 0.0;
     }
     wsync();
     bool bad = false;
     double lsum = 0.0;
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) {
+    for (int kb = 0; kb < NB; ++kb) {
         double* Dg = T + 16 * kb * ld + 16 * kb;
         // (1) factor the 16 x 16 diagonal block; lane r (r = lr) keeps row r
         double d[16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) d[k] = (k <= lr) ? Dg[lr * ld + k] : 0.0;
+        double pp = 1.0;  // product of four pivots: one logarithm per four columns
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const double piv = bcast(d[j], j);
             bad = bad || !(piv > 0.0);
-            const double sd = sqrt(piv > 0.0 ? piv : 1.0);
-            lsum += log(sd);
+            const double pv = piv > 0.0 ? piv : 1.0;
+            const double sd = sqrt(pv);
+            pp *= pv;
+            if ((j & 3) == 3) {
+                lsum += 0.5 * log(pp);
+                pp = 1.0;
+            }
             const double rs = 1.0 / sd;
             const double lij = (lr > j) ? d[j] * rs : (lr == j ? sd : 0.0);
             d[j] = lij;
@@ -367,7 +375,7 @@ __device__ __forceinline__ bool wave_chol_inv64(double* T, int ld, int n, double
         wsync();
         // (3) panel: L_ib = A_ib D^{-T} for the blocks below
 #pragma unroll
-        for (int ib = kb + 1; ib < 4; ++ib) {
+        for (int ib = kb + 1; ib < NB; ++ib) {
             v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -378,9 +386,9 @@ __device__ __forceinline__ bool wave_chol_inv64(double* T, int ld, int n, double
         wsync();
         // (4) trailing blocks: A_ij -= L_ik L_jk^T
 #pragma unroll
-        for (int jb = kb + 1; jb < 4; ++jb)
+        for (int jb = kb + 1; jb < NB; ++jb)
 #pragma unroll
-            for (int ib = jb; ib < 4; ++ib) {
+            for (int ib = jb; ib < NB; ++ib) {
                 v4d acc;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) acc[i] = T[(16 * ib + lg + 4 * i) * ld + 16 * jb + lr];
@@ -395,8 +403,8 @@ __device__ __forceinline__ bool wave_chol_inv64(double* T, int ld, int n, double
     }
     // (5) off-diagonal blocks of L^{-1}, block row by block row
 #pragma unroll
-    for (int ib = 1; ib < 4; ++ib) {
-        v4d out[3];
+    for (int ib = 1; ib < NB; ++ib) {
+        v4d out[NB > 1 ? NB - 1 : 1];
 #pragma unroll
         for (int jb = 0; jb < ib; ++jb) {
             v4d y = v4d{0.0, 0.0, 0.0, 0.0};
@@ -418,13 +426,17 @@ __device__ __forceinline__ bool wave_chol_inv64(double* T, int ld, int n, double
         wsync();
     }
     // zeros above the diagonal blocks
-    for (int e = lane; e < 64 * 64; e += 64) {
-        const int i = e >> 6, j = e & 63;
+    for (int e = lane; e < NT16 * NT16; e += 64) {
+        const int i = e / NT16, j = e % NT16;
         if ((j >> 4) > (i >> 4)) T[i * ld + j] = 0.0;
     }
     wsync();
     *logdet = lsum;
     return bad;
+}
+
+__device__ __forceinline__ bool wave_chol_inv64(double* T, int ld, int n, double* logdet) {
+    return wave_chol_inv<4>(T, ld, n, logdet);
 }
 
 // Load an n x n lower triangle (generic pointer, ldg) into LDS (ld), zero

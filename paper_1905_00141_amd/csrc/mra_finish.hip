@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(NT) k_prior_finish_w(KArgs a) {
 enum { FIN_LEAF = 0, FIN_FOLD = 1 };
 
 template <int NMAX, int MODE>
-__global__ void __launch_bounds__(NT, (NMAX <= 32 ? 2 : 1)) k_small(KArgs a) {
+__global__ void __launch_bounds__(NT, (NMAX <= 32 ? 3 : 1)) k_small(KArgs a) {
     constexpr int LDT = NMAX + 1;
     constexpr int NR = NMAX / 16;
     __shared__ double T[4][NMAX * LDT];
@@ -175,12 +175,10 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 2 : 1)) k_small(KArgs a) {
                 }
         }
         wsync();
-        const bool bad = wave_potrf_inv<NMAX>(Tw, LDT, Tiw, LDT, NMAX);
+        // the tile is replaced by L^{-1}
+        double ldv = 0.0;
+        const bool bad = wave_chol_inv<NR>(Tw, LDT, n, &ldv);
         if (bad && lane == 0) atomicCAS(a.status + th, 0, int(g + 1));
-        // the tile now holds L^{-1}: log det = -2 sum log diag(L^{-1})
-        double ldv = (lane < n) ? -log(Tw[lane * LDT + lane]) : 0.0;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) ldv += __shfl_xor(ldv, off);
         if (lane == 0) a.dval[th * a.d_stride + g] = 2.0 * ldv;
         if (MODE == FIN_LEAF) {
             if (lane < n) Fr[int64_t(lane) * a.WFs + (a.WF - 1)] = a.z[lo + lane];
@@ -242,7 +240,7 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 2 : 1)) k_small(KArgs a) {
 // matrix product runs on the matrix cores; the k index of a 16-wide step is
 // permuted the same way on both operands (lane group g holds k = 4g .. 4g+3),
 // so that F rows are loaded four consecutive doubles at a time.
-constexpr int FPD = 65;  // LDS pitch of the 64-column tiles
+constexpr int FPD = 66;  // LDS pitch of the 64-column tiles (matrix-core operand reads hit each bank twice)
 
 template <int MODE>
 __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn, double* red, int* flag) {
@@ -351,132 +349,188 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
             __syncthreads();
             if (*flag) { failed = true; break; }
             logdet += red[0];
-            // c. right-hand sides of the block rows: X_k <- L_kk^{-1} X_k
-            for (int sl = w; sl < nsl; sl += 4) {
-                const int c = xc0 + 16 * sl + lr;
-                const bool cok = c < a.WF;
-                v4d xv[4];
+            // the panel below, 64 rows (a chunk) at a time:
+            //   P = A[r0 .., j0 ..] L_kk^{-T} into LDS (wave w forms rows
+            //   r0 + 16 w .. + 15) and into the scratch slot
+            auto panel = [&](int r0) {
+                const int r = r0 + 16 * w + lr;
+                const bool rok = r < n;
+                const double* ra = Ag + (rok ? int64_t(r) * lda : 0) + j0;
+                v4d acc[4];
 #pragma unroll
-                for (int t2 = 0; t2 < 4; ++t2)
+                for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int rr = 16 * t2 + lg + 4 * i;
-                        xv[t2][i] = ldg0(Fr, int64_t(j0 + rr) * a.WFs + c, cok && rr < jb);
-                    }
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 16 * kk + 4 * lg;
+                    double av[4];
 #pragma unroll
-                for (int t2 = 0; t2 < 4; ++t2) {
-                    if (16 * t2 >= jb) break;
-                    v4d o = v4d{0.0, 0.0, 0.0, 0.0};
+                    for (int j = 0; j < 4; ++j) av[j] = (rok && k + j < jb) ? ra[k + j] : 0.0;
 #pragma unroll
-                    for (int k2 = 0; k2 <= t2; ++k2)
+                    for (int j = 0; j < 4; ++j)
 #pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            o = mfma(Tt[(16 * t2 + lr) * FPD + 16 * k2 + 4 * q + lg], xv[k2][q], o);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int rr = 16 * t2 + lg + 4 * i;
-                        if (cok && rr < jb) Fr[int64_t(j0 + rr) * a.WFs + c] = o[i];
-                    }
+                        for (int c = 0; c < 4; ++c) acc[c] = mfma(av[j], Tt[(16 * c + lr) * FPD + k + j], acc[c]);
                 }
-            }
-            __syncthreads();
-            // d. the panel below, 64 rows at a time
-            for (int r0 = j0 + 64; r0 < n; r0 += 64) {
-                // i. P = A[r0 .., j0 ..] L_kk^{-T}: wave w forms rows r0 + 16 w .. + 15
-                {
-                    const int r = r0 + 16 * w + lr;
-                    const bool rok = r < n;
-                    const double* ra = Ag + (rok ? int64_t(r) * lda : 0) + j0;
-                    v4d acc[4];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int rr = 16 * w + lg + 4 * i, cc = 16 * c + lr;
+                        Pn[rr * FPD + cc] = acc[c][i];
+                        if (r0 + rr < n) Ag[int64_t(r0 + rr) * lda + j0 + cc] = acc[c][i];
+                    }
+            };
+            //   trailing triangle of the chunk's rows: A[r][c] -= P_r . P_c for
+            //   j0 + 64 <= c <= r (P_c from LDS for this chunk, from the
+            //   scratch slot for earlier chunks)
+            auto syrk = [&](int r0) {
+                const int R = r0 + 16 * w;
+                if (R >= n) return;
+#pragma unroll 1
+                for (int cb0 = j0 + 64; cb0 <= r0; cb0 += 64) {
+                    const bool here = cb0 == r0;
+                    v4d acc[4];
+                    bool tok[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int c0 = cb0 + 16 * c;
+                        tok[c] = c0 < n && c0 <= R + 15;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int rr = R + lg + 4 * i, cc = c0 + lr;
+                            acc[c][i] = ldg0(Ag, int64_t(rr) * lda + cc, tok[c] && rr < n && cc < n && cc <= rr);
+                        }
+                    }
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) {
                         const int k = 16 * kk + 4 * lg;
-                        double av[4];
+                        double av[4], bv[4][4];
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) av[j] = (rok && k + j < jb) ? ra[k + j] : 0.0;
+                        for (int j = 0; j < 4; ++j) av[j] = Pn[(16 * w + lr) * FPD + k + j];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const int cr = 16 * c + lr;  // row of P within its chunk
+                            if (here) {
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) bv[c][j] = Pn[cr * FPD + k + j];
+                            } else {
+                                const bool ok = tok[c] && cb0 + cr < n;
+                                const v4d v = *reinterpret_cast<const v4d*>(Ag + (ok ? int64_t(cb0 + cr) * lda + j0 + k : 0));
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) bv[c][j] = ok ? v[j] : 0.0;
+                            }
+                        }
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
 #pragma unroll
-                            for (int c = 0; c < 4; ++c) acc[c] = mfma(av[j], Tt[(16 * c + lr) * FPD + k + j], acc[c]);
+                            for (int c = 0; c < 4; ++c) acc[c] = mfma(-av[j], bv[c][j], acc[c]);
                     }
 #pragma unroll
                     for (int c = 0; c < 4; ++c)
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            const int rr = 16 * w + lg + 4 * i, cc = 16 * c + lr;
-                            Pn[rr * FPD + cc] = acc[c][i];
-                            if (r0 + rr < n) Ag[int64_t(r0 + rr) * lda + j0 + cc] = acc[c][i];
+                            const int rr = R + lg + 4 * i, cc = cb0 + 16 * c + lr;
+                            if (tok[c] && rr < n && cc < n && cc <= rr) Ag[int64_t(rr) * lda + cc] = acc[c][i];
                         }
                 }
+            };
+            // c. the first chunk's panel and trailing triangle
+            const int r1 = j0 + 64;
+            const bool chunk1 = r1 < n;
+            if (chunk1) {
+                panel(r1);
                 __syncthreads();
-                // ii. trailing triangle of these rows: A[r][c] -= P_r . P_c for
-                // j0 + 64 <= c <= r (P_c from LDS for this chunk, from the
-                // scratch slot for earlier chunks)
-                {
-                    const int R = r0 + 16 * w;
-                    if (R < n) {
-                        for (int cb0 = j0 + 64; cb0 <= r0; cb0 += 64) {
-                            const bool here = cb0 == r0;
-                            v4d acc[4];
-                            bool tok[4];
+                syrk(r1);
+            }
+            // d. right-hand sides: X_k <- L_kk^{-1} X_k, then (fused) the first
+            // chunk's rows X_r -= P_r X_k with the solved tiles as the second
+            // operand; each wave a 16-column slice at a time, the next slice's
+            // rows loaded while the current one is computed
+            {
+                // row r of a slice: base + (r - lg) * WFs with a per-lane base
+                // and a uniform offset (no per-row address kept live)
+                const int64_t s4 = int64_t(4) * a.WFs;
+                auto load_k = [&](int sl, v4d (&v)[4]) {
+                    const int c = xc0 + 16 * sl + lr;
+                    const bool cok = sl < nsl && c < a.WF;
+                    const double* b = cok ? Fr + int64_t(j0 + lg) * a.WFs + c : Fr;
 #pragma unroll
-                            for (int c = 0; c < 4; ++c) {
-                                const int c0 = cb0 + 16 * c;
-                                tok[c] = c0 < n && c0 <= R + 15;
+                    for (int t2 = 0; t2 < 4; ++t2)
 #pragma unroll
-                                for (int i = 0; i < 4; ++i) {
-                                    const int rr = R + lg + 4 * i, cc = c0 + lr;
-                                    acc[c][i] = ldg0(Ag, int64_t(rr) * lda + cc, tok[c] && rr < n && cc < n && cc <= rr);
-                                }
-                            }
-#pragma unroll
-                            for (int kk = 0; kk < 4; ++kk) {
-                                const int k = 16 * kk + 4 * lg;
-                                double av[4], bv[4][4];
-#pragma unroll
-                                for (int j = 0; j < 4; ++j) av[j] = Pn[(16 * w + lr) * FPD + k + j];
-#pragma unroll
-                                for (int c = 0; c < 4; ++c) {
-                                    const int cr = 16 * c + lr;  // row of P within its chunk
-                                    if (here) {
-#pragma unroll
-                                        for (int j = 0; j < 4; ++j) bv[c][j] = Pn[cr * FPD + k + j];
-                                    } else {
-                                        const bool ok = tok[c] && cb0 + cr < n;
-                                        const v4d v = *reinterpret_cast<const v4d*>(Ag + (ok ? int64_t(cb0 + cr) * lda + j0 + k : 0));
-#pragma unroll
-                                        for (int j = 0; j < 4; ++j) bv[c][j] = ok ? v[j] : 0.0;
-                                    }
-                                }
-#pragma unroll
-                                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                                    for (int c = 0; c < 4; ++c) acc[c] = mfma(-av[j], bv[c][j], acc[c]);
-                            }
-#pragma unroll
-                            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                                for (int i = 0; i < 4; ++i) {
-                                    const int rr = R + lg + 4 * i, cc = cb0 + 16 * c + lr;
-                                    if (tok[c] && rr < n && cc < n && cc <= rr) Ag[int64_t(rr) * lda + cc] = acc[c][i];
-                                }
+                        for (int i = 0; i < 4; ++i) {
+                            const bool ok = cok && 16 * t2 + lg + 4 * i < jb;
+                            const double vv = b[ok ? (4 * t2 + i) * s4 : 0];
+                            v[t2][i] = ok ? vv : 0.0;
                         }
-                    }
-                }
-                // iii. right-hand sides of these rows: X_r -= P_r X_k
+                };
+                v4d xv[4];
+                load_k(w, xv);
+#pragma unroll 1
                 for (int sl = w; sl < nsl; sl += 4) {
                     const int c = xc0 + 16 * sl + lr;
                     const bool cok = c < a.WF;
-                    double xb[4][4];  // X_k[16 kk + 4 lg + j][c]
+                    v4d xr[4];
+                    const double* bk = cok ? Fr + int64_t(j0 + lg) * a.WFs + c : Fr;  // rows of block k
+                    const double* b1 = cok ? Fr + int64_t(r1 + lg) * a.WFs + c : Fr;  // rows of the first chunk
+                    if (chunk1) {
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk)
+                        for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int k = 16 * kk + 4 * lg + j;
-                            xb[kk][j] = ldg0(Fr, int64_t(j0 + k) * a.WFs + c, cok && k < jb);
+                            for (int i = 0; i < 4; ++i) {
+                                const bool ok = cok && r1 + 16 * rt + lg + 4 * i < n;
+                                const double vv = b1[ok ? (4 * rt + i) * s4 : 0];
+                                xr[rt][i] = ok ? vv : 0.0;
+                            }
+                    }
+                    v4d xn[4];
+                    load_k(sl + 4, xn);
+                    v4d o[4];
+#pragma unroll
+                    for (int t2 = 0; t2 < 4; ++t2) {
+                        o[t2] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int k2 = 0; k2 <= t2; ++k2)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                o[t2] = mfma(Tt[(16 * t2 + lr) * FPD + 16 * k2 + 4 * q + lg], xv[k2][q], o[t2]);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (cok && 16 * t2 + lg + 4 * i < jb) const_cast<double*>(bk)[(4 * t2 + i) * s4] = o[t2][i];
+                    }
+                    if (chunk1) {
+#pragma unroll
+                        for (int rt = 0; rt < 4; ++rt) {
+#pragma unroll
+                            for (int t2 = 0; t2 < 4; ++t2)
+#pragma unroll
+                                for (int q = 0; q < 4; ++q)
+                                    xr[rt] = mfma(-Pn[(16 * rt + lr) * FPD + 16 * t2 + 4 * q + lg], o[t2][q], xr[rt]);
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                if (cok && r1 + 16 * rt + lg + 4 * i < n) const_cast<double*>(b1)[(4 * rt + i) * s4] = xr[rt][i];
                         }
+                    }
+#pragma unroll
+                    for (int t2 = 0; t2 < 4; ++t2) xv[t2] = xn[t2];
+                }
+            }
+            __syncthreads();
+            // e. further chunks: panel, trailing triangle, right-hand sides
+            // (X_k read back from memory)
+#pragma unroll 1
+            for (int r0 = r1 + 64; r0 < n; r0 += 64) {
+                panel(r0);
+                __syncthreads();
+                syrk(r0);
+#pragma unroll 1
+                for (int sl = w; sl < nsl; sl += 4) {
+                    const int c = xc0 + 16 * sl + lr;
+                    const bool cok = c < a.WF;
+                    double xb[4][4];  // X_k[16 t2 + 4 q + lg][c]
+#pragma unroll
+                    for (int t2 = 0; t2 < 4; ++t2)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            xb[t2][q] = ldg0(Fr, int64_t(j0 + 16 * t2 + 4 * q + lg) * a.WFs + c, cok);
 #pragma unroll
                     for (int rt = 0; rt < 4; ++rt) {
                         if (r0 + 16 * rt >= n) break;
@@ -487,10 +541,10 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
                             o[i] = ldg0(Fr, int64_t(rr) * a.WFs + c, cok && rr < n);
                         }
 #pragma unroll
-                        for (int kk = 0; kk < 4; ++kk)
+                        for (int t2 = 0; t2 < 4; ++t2)
 #pragma unroll
-                            for (int j = 0; j < 4; ++j)
-                                o = mfma(-Pn[(16 * rt + lr) * FPD + 16 * kk + 4 * lg + j], xb[kk][j], o);
+                            for (int q = 0; q < 4; ++q)
+                                o = mfma(-Pn[(16 * rt + lr) * FPD + 16 * t2 + 4 * q + lg], xb[t2][q], o);
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const int rr = r0 + 16 * rt + lg + 4 * i;
