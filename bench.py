@@ -46,10 +46,26 @@ def canonical_flops(leaf_counts, J, M, p):
     return total
 
 
-def cpu_baseline(cfg, theta, budget_s=25.0):
-    """The oracle, single-threaded, on whole subtrees of the same tree.  Evals/s
-    is extrapolated from the subtree's share of the canonical flops."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, theta, budget_s=12.0):
+    """The oracle on whole subtrees of the same tree: first single-threaded
+    (the subtree is grown until it takes a bounded time), then the same subtree
+    on every host core at once (one oracle call per thread, each with its own
+    theta; the oracle is plain sequential C, so this is the all-core
+    throughput).  Evals/s is extrapolated from the subtree's share of the
+    canonical flops."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as o
 
     fam = o.MATERN
@@ -76,15 +92,27 @@ def cpu_baseline(cfg, theta, budget_s=25.0):
         if dt >= 0.35 * budget_s or spent + 4.5 * dt > budget_s:
             break
     est = done["seconds"] * full / done["flops"]
+    # the same subtree on every core: distinct theta (ranges spread over the box)
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    ths = [np.array([1.0, b, theta[2]]) for b in np.exp(np.linspace(np.log(0.02), np.log(0.3), ncores))]
+    t1 = time.time()
+    with ThreadPoolExecutor(max_workers=ncores) as ex:
+        list(ex.map(lambda th: o.subtree_du(ot, th, done["level"], done["k"], fam, cfg["nu"]), ths))
+    wall = time.time() - t1
+    all_rate = ncores / (wall * full / done["flops"])
+    log(f"[cpu_baseline] {ncores} threads: {ncores} subtree evaluations in {wall:.2f} s ({cpu_model()})")
     return {
-        "value": 1.0 / est,
+        "value": all_rate,
         "unit": "evals/s",
-        "cores": 1,
+        "cores": ncores,
         "kind": "oracle",
-        "sample": (f"one theta (alpha=1, range={theta[1]:.3g}, nugget={theta[2]:.3g}) on the subtree of "
-                   f"level-{done['level']} region {done['k']} ({done['n_obs']} of {int(counts.sum())} obs), "
-                   f"{done['seconds']:.2f} s single-threaded; scaled to the whole tree by canonical flops "
-                   f"({done['flops']:.3g} of {full:.3g}); oracle tree build {build_s:.1f} s not counted"),
+        "single_core_value": 1.0 / est,
+        "cpu": cpu_model(),
+        "sample": (f"the subtree of level-{done['level']} region {done['k']} ({done['n_obs']} of "
+                   f"{int(counts.sum())} obs): one theta (alpha=1, range={theta[1]:.3g}, nugget={theta[2]:.3g}) "
+                   f"single-threaded in {done['seconds']:.2f} s, then {ncores} theta on {ncores} threads at once in "
+                   f"{wall:.2f} s; scaled to the whole tree by canonical flops ({done['flops']:.3g} of {full:.3g}); "
+                   f"oracle tree build {build_s:.1f} s not counted"),
     }
 
 
@@ -155,9 +183,12 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="run the execution-plan autotuner on 4 of the theta before timing (about a minute; "
                          "on this workload it keeps the default plan)")
-    ap.add_argument("--mle", action="store_true",
-                    help="also run the MLE searches on the same tree (32x32 profiled grid, Nelder-Mead without and "
-                         "with the surrogate trained on 2048 exact evaluations) and report exact-evaluation counts")
+    ap.add_argument("--no-mle", action="store_true",
+                    help="skip the MLE searches that follow the timed steps by default on the same tree (32x32 "
+                         "profiled grid, Nelder-Mead, trust region, the surrogate's sequential design; exact-"
+                         "evaluation counts in the JSON line)")
+    ap.add_argument("--mle-pretrained", action="store_true",
+                    help="also run the surrogate trained once on 2048 exact evaluations as a Nelder-Mead start")
     ap.add_argument("--predict", action="store_true",
                     help="also time kriging on the n = 131072, M = 7 uniform workload at its 16384 held-out points")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -218,8 +249,17 @@ def main():
             f"{s['ms']:10.3f} ms  {100 * s['ms'] / max(tot_ms, 1e-9):5.1f}%  {tf:7.3f} TF/s")
     dom0 = max(breakdown, key=lambda s: s["ms"])
 
-    # timed region: HIP events only around the dominant kernel's launches
+    # one more step with HIP events around the dominant kernel's launches only
+    # (its duration for the roofline); profiling disables graph capture
     mra.profile_enable(True, dom0["name"], dom0["level"])
+    tree.loglik(theta, cfg["family"], cfg["nu"], out=out, stream=stream)
+    stream.synchronize()
+    mra.profile_enable(False)
+    stats = mra.profile_read()
+    # timed region: repeated device-pointer calls on one stream replay the
+    # captured graph of the whole launch sequence (captured by the first call)
+    tree.loglik(theta, cfg["family"], cfg["nu"], out=out, stream=stream)
+    stream.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -228,8 +268,6 @@ def main():
         log(f"[bench] step {i} done at {time.perf_counter() - t0:.3f} s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    mra.profile_enable(False)
-    stats = mra.profile_read()
     ms_step = 1000.0 * elapsed / args.steps
     value = B * args.steps / elapsed
 
@@ -246,8 +284,17 @@ def main():
         "launches": dom["launches"],
         "avg_launch_ms": dom["ms"] / dom["launches"],
         "flops_per_launch": dom["flops"] / dom["launches"],
-        "share_of_step": dom["ms"] / (1000.0 * elapsed),
+        "share_of_step": dom["ms"] / ms_step,
+        "timing": "HIP events on the library's stream around that kernel's launches in a separate profiled step; "
+                  "the timed steps replay the captured graph without events",
     }
+    try:
+        mp = mra.mfma_peak_tflops()
+        roof["measured_peak"] = mp
+        roof["frac_of_measured_peak"] = ach / mp
+        log(f"[bench] measured FP64 matrix-core rate {mp:.1f} TFLOP/s")
+    except mra.MraError as e:
+        log(f"[bench] matrix-core rate not measured: {e}")
     all_flops = sum(s["flops"] for s in breakdown)
     res = {
         "metric": METRIC,
@@ -266,7 +313,7 @@ def main():
             "workload": cfg["name"], "n": int(n), "n_used": int(info["n_used"]), "M": M, "J": 4, "r": 64,
             "r_hat": int(info["r_hat"]), "n_theta": int(B), "family": "matern", "nu": 1.5,
             "leaf_obs_min": int(info["leaf_min"]), "leaf_obs_max": int(info["leaf_max"]),
-            "whole_path_tflops": all_flops * args.steps / elapsed / 1e12,
+            "whole_path_tflops": all_flops / (ms_step * 1e-3) / 1e12,
             "plan": None if tune is None else {"fold_max": tune["fold_max"], "small_max": tune["small_max"]},
         },
         "roofline": roof,
@@ -284,10 +331,11 @@ def main():
         log(f"[bench] copy calibration: fill and copy of {args.copy_calibration} MiB")
     if args.predict:
         res["predict"] = bench_predict(mra, synth, torch, dev)
-    if args.mle:
+    if not args.no_mle:
         from paper_1905_00141_amd import mle
         t0 = time.time()
-        res["mle"] = mle.run(tree, cfg["family"], cfg["nu"], n_train=2048, train_steps=3000, log=log)
+        res["mle"] = mle.run(tree, cfg["family"], cfg["nu"], n_train=2048, train_steps=3000, log=log,
+                             pretrained=args.mle_pretrained)
         res["mle"]["wall_s"] = time.time() - t0
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(cfg, cfg["theta"][0])

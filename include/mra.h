@@ -245,6 +245,15 @@ typedef struct mra_kernel_stat {
 int mra_profile_enable(int on, const char *only_kernel, int only_level);
 int mra_profile_read(mra_kernel_stat *out, int cap, int *count);
 
+/*
+ * Achievable FP64 matrix-core rate of the current device, for measurement:
+ * 8 workgroups of 4 waves per compute unit each issue `iters` rounds of 8
+ * independent 16x16x4 FP64 matrix instructions on register operands; *tflops
+ * receives (flops issued) / (kernel time).  Allocates and frees a small
+ * output buffer.  Errors: MRA_EINVAL, MRA_EDEVICE, MRA_ENOMEM.
+ */
+int mra_bench_mfma_f64(int64_t iters, double *tflops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -447,18 +447,20 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
             // rows loaded while the current one is computed
             {
                 // row r of a slice: base + (r - lg) * WFs with a per-lane base
-                // and a uniform offset (no per-row address kept live)
+                // and a uniform offset (no per-row address kept live); a
+                // masked lane reads the region's first element instead (the
+                // base itself may lie past the region's last row)
                 const int64_t s4 = int64_t(4) * a.WFs;
                 auto load_k = [&](int sl, v4d (&v)[4]) {
                     const int c = xc0 + 16 * sl + lr;
                     const bool cok = sl < nsl && c < a.WF;
-                    const double* b = cok ? Fr + int64_t(j0 + lg) * a.WFs + c : Fr;
+                    const double* b = Fr + int64_t(j0 + lg) * a.WFs + c;
 #pragma unroll
                     for (int t2 = 0; t2 < 4; ++t2)
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const bool ok = cok && 16 * t2 + lg + 4 * i < jb;
-                            const double vv = b[ok ? (4 * t2 + i) * s4 : 0];
+                            const double vv = *(ok ? b + (4 * t2 + i) * s4 : Fr);
                             v[t2][i] = ok ? vv : 0.0;
                         }
                 };
@@ -469,15 +471,15 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
                     const int c = xc0 + 16 * sl + lr;
                     const bool cok = c < a.WF;
                     v4d xr[4];
-                    const double* bk = cok ? Fr + int64_t(j0 + lg) * a.WFs + c : Fr;  // rows of block k
-                    const double* b1 = cok ? Fr + int64_t(r1 + lg) * a.WFs + c : Fr;  // rows of the first chunk
+                    double* bk = Fr + int64_t(j0 + lg) * a.WFs + c;  // rows of block k (stores only when valid)
+                    double* b1 = Fr + int64_t(r1 + lg) * a.WFs + c;  // rows of the first chunk
                     if (chunk1) {
 #pragma unroll
                         for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
                                 const bool ok = cok && r1 + 16 * rt + lg + 4 * i < n;
-                                const double vv = b1[ok ? (4 * rt + i) * s4 : 0];
+                                const double vv = *(ok ? b1 + (4 * rt + i) * s4 : Fr);
                                 xr[rt][i] = ok ? vv : 0.0;
                             }
                     }
@@ -494,7 +496,7 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
                                 o[t2] = mfma(Tt[(16 * t2 + lr) * FPD + 16 * k2 + 4 * q + lg], xv[k2][q], o[t2]);
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
-                            if (cok && 16 * t2 + lg + 4 * i < jb) const_cast<double*>(bk)[(4 * t2 + i) * s4] = o[t2][i];
+                            if (cok && 16 * t2 + lg + 4 * i < jb) bk[(4 * t2 + i) * s4] = o[t2][i];
                     }
                     if (chunk1) {
 #pragma unroll
@@ -506,7 +508,7 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
                                     xr[rt] = mfma(-Pn[(16 * rt + lr) * FPD + 16 * t2 + 4 * q + lg], o[t2][q], xr[rt]);
 #pragma unroll
                             for (int i = 0; i < 4; ++i)
-                                if (cok && r1 + 16 * rt + lg + 4 * i < n) const_cast<double*>(b1)[(4 * rt + i) * s4] = xr[rt][i];
+                                if (cok && r1 + 16 * rt + lg + 4 * i < n) b1[(4 * rt + i) * s4] = xr[rt][i];
                         }
                     }
 #pragma unroll

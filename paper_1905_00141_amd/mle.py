@@ -12,15 +12,21 @@ scales with alpha, so
 with D, Q the log-determinant and quadratic form at alpha = 1; it peaks at
 alpha_hat = Q / n.  The searches therefore run in the plane (log beta, log lam).
 
-Three searches, each counting exact evaluations:
+Searches, each counting exact evaluations and the sequential calls they need:
   * grid: the plain 32 x 32 grid over (beta, lam), log-spaced;
   * local: a derivative-free Nelder-Mead search on exact values from the
-    centre of the box (the method without the surrogate);
-  * surrogate: the network (include/mra_mlp.h) is trained on exact
-    log-likelihoods (monotonically compressed near their maximum) at Sobol
-    points of the (log alpha, log beta, log tau) box,
-    its maximum over a dense grid is the proposal, and the same Nelder-Mead
-    search on exact values starts there with a smaller simplex.
+    centre of the box (a method without the surrogate);
+  * trust region: a derivative-free trust-region search with quadratic
+    interpolation models in the box, after Powell's methods (UOBYQA 2002,
+    BOBYQA 2009; the paper's optimisation mode uses BOBYQA, Sec. 2.2);
+  * surrogate (sequential design): the network (include/mra_mlp.h) is fitted
+    to the exact values of a 64-point Sobol design of the box, proposes the
+    maximum of its prediction and a few distinct near-maximal points, the
+    exact MRA evaluates them in one batch, the network is refitted, and so
+    on until the best exact value stops improving;
+  * surrogate (pre-trained): the network trained once on 2048 exact values
+    in the (log alpha, log beta, log tau) box proposes a start for
+    Nelder-Mead (kept for comparison; its training set outweighs the grid).
 The exact MRA stays the judge of every reported value.
 
 This module is orchestration only: every log-likelihood and every network
@@ -52,12 +58,14 @@ class ExactObjective:
         self.tree, self.family, self.nu = tree, family, nu
         self.n = float(tree.info["n_used"])
         self.evals = 0
+        self.calls = 0     # sequential exact calls (batches)
         self.history = []  # (eval count after the batch, best value so far)
         self.best = -np.inf
         self.best_x = None
 
     def __call__(self, X):
         X = np.atleast_2d(np.asarray(X, dtype=np.float64))
+        self.calls += 1
         th = np.stack([np.ones(len(X)), np.exp(X[:, 0]), np.exp(X[:, 1])], axis=1)
         _, ld, q = self.tree.loglik_terms(th, self.family, self.nu)
         ahat = q / self.n
@@ -166,6 +174,171 @@ def nelder_mead(obj, x0, step, tol=0.02, max_evals=400):
     return S[i], float(F[i])
 
 
+def trust_region(obj, x0, rho_beg, rho_end=1e-3, max_evals=200, lo=None, hi=None):
+    """Derivative-free trust-region maximisation in a box with quadratic
+    interpolation models (after Powell's UOBYQA and BOBYQA).  The model
+    q(x) = c + g.(x - xb) + (x - xb)^T H (x - xb) / 2 interpolates the
+    objective at (n+1)(n+2)/2 points around the best point xb; each iteration
+    maximises q over the trust region |d| <= delta intersected with the box,
+    evaluates the step, compares the actual with the predicted increase to
+    enlarge or shrink delta, and replaces the interpolation point farthest
+    from the best one (or, when the model step is too short, moves that point
+    to a distance delta along a coordinate to restore the geometry).  Stops
+    when delta falls below rho_end or the budget is spent."""
+    if lo is None or hi is None:
+        lo, hi = box2()
+    lo, hi = np.asarray(lo, dtype=np.float64), np.asarray(hi, dtype=np.float64)
+    n = len(lo)
+    x0 = np.clip(np.asarray(x0, dtype=np.float64), lo, hi)
+    scale = hi - lo
+
+    def clip(p, ref):
+        q = np.clip(p, lo, hi)
+        if np.allclose(q, ref):
+            q = np.clip(ref - (p - ref), lo, hi)
+        return q
+
+    pts = [x0]
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = rho_beg * scale[i]
+        pts.append(clip(x0 + e, x0))
+        pts.append(clip(x0 - e, x0))
+    for i in range(n):
+        for j in range(i + 1, n):
+            e = np.zeros(n)
+            e[i], e[j] = rho_beg * scale[i], rho_beg * scale[j]
+            pts.append(clip(x0 + e, x0))
+    Y = np.array(pts)
+    F = np.asarray(obj(Y), dtype=np.float64)
+    delta = rho_beg
+
+    def basis(D):  # quadratic monomials of the scaled displacement
+        cols = [np.ones(len(D))] + [D[:, i] for i in range(n)]
+        cols += [D[:, i] * D[:, j] * (0.5 if i == j else 1.0) for i in range(n) for j in range(i, n)]
+        return np.stack(cols, axis=1)
+
+    while obj.evals < max_evals and delta >= rho_end:
+        b = int(np.argmax(F))
+        xb, fb = Y[b], F[b]
+        D = (Y - xb) / scale
+        coef, *_ = np.linalg.lstsq(basis(D), F, rcond=None)
+        g = coef[1:1 + n]
+        H = np.zeros((n, n))
+        k = 1 + n
+        for i in range(n):
+            for j in range(i, n):
+                H[i, j] = H[j, i] = coef[k]
+                k += 1
+        q = lambda d: float(coef[0] + g @ d + 0.5 * d @ H @ d)
+        # trust-region step: the better of the model's stationary point (if
+        # it is a maximum inside the region) and a dense search of the
+        # region's boundary, each kept inside the box
+        cands = []
+        try:
+            s = -np.linalg.solve(H, g)
+            if np.all(np.linalg.eigvalsh(H) < 0) and np.linalg.norm(s) <= delta:
+                cands.append(s)
+        except np.linalg.LinAlgError:
+            pass
+        ang = np.linspace(0.0, 2.0 * np.pi, 256, endpoint=False)
+        if n == 2:
+            ring = np.stack([np.cos(ang), np.sin(ang)], axis=1)
+        else:
+            ring = np.random.default_rng(0).standard_normal((512, n))
+            ring /= np.linalg.norm(ring, axis=1, keepdims=True)
+        for fr in (1.0, 0.5, 0.25):
+            cands.extend(list(ring * delta * fr))
+        dl, dh = (lo - xb) / scale, (hi - xb) / scale
+        cands = [np.clip(c, dl, dh) for c in cands]
+        d = max(cands, key=q)
+        pred = q(d) - fb
+        if np.linalg.norm(d) < 0.1 * delta or pred <= 1e-12:
+            # model step too short: improve the geometry, then shrink
+            far = int(np.argmax(np.linalg.norm(D, axis=1)))
+            if np.linalg.norm(D[far]) > 2.0 * delta:
+                e = np.zeros(n)
+                e[obj.evals % n] = delta
+                Y[far] = clip(xb + e * scale, xb)
+                F[far] = float(obj(Y[far])[0])
+            else:
+                delta *= 0.5
+            continue
+        xn = xb + d * scale
+        fn = float(obj(xn)[0])
+        ratio = (fn - fb) / pred
+        if ratio > 0.7 and np.linalg.norm(d) > 0.9 * delta:
+            delta = min(2.0 * delta, 0.5)
+        elif ratio < 0.1:
+            delta *= 0.5
+        # replace the point farthest from the (new) best point
+        ref = xn if fn > fb else xb
+        dist = np.linalg.norm((Y - ref) / scale, axis=1)
+        if fn <= fb:
+            dist[b] = -1.0
+        far = int(np.argmax(dist))
+        Y[far], F[far] = xn, fn
+    b = int(np.argmax(F))
+    return Y[b], float(F[b])
+
+
+def surrogate_sequential(tree: mra.Tree, family="matern", nu=1.5, n_init=64, per_round=8, max_rounds=12,
+                         steps_first=1500, steps=400, lr=3e-3, seed=5, log=None):
+    """Sequential design with the network in the profiled plane (log beta,
+    log lam): fit, propose the maximum of the prediction and near-maximal
+    points at least a grid step apart from every evaluated point, evaluate
+    them exactly in one batch, refit.  Stops after two rounds without an
+    improvement of 0.05 nats.  Returns (objective, best x, best value, net)."""
+    obj = ExactObjective(tree, family, nu)
+    lo, hi = box2()
+    from scipy.stats import qmc
+    X = lo + qmc.Sobol(d=2, scramble=True, seed=seed).random(n_init) * (hi - lo)
+    F = np.asarray(obj(X), dtype=np.float64)
+    lo3 = np.array([-1.0, lo[0], lo[1]])
+    hi3 = np.array([1.0, hi[0], hi[1]])
+    net = mra.Mlp(synth.mlp_init(seed))
+    k = 128
+    gx = np.linspace(lo[0], hi[0], k)
+    gy = np.linspace(lo[1], hi[1], k)
+    G = np.array([(u, v) for u in gx for v in gy])
+    G3 = np.concatenate([np.zeros((len(G), 1)), G], axis=1).astype(np.float32)
+    min_sep = 1.5 * (hi - lo) / (k - 1)
+    stall = 0
+    for r in range(max_rounds):
+        yt = -np.log1p((F.max() - F) / TARGET_SCALE)
+        net.set_scaling(lo3, hi3, float(yt.mean()), float(yt.std()))
+        x3 = np.concatenate([np.zeros((len(X), 1)), X], axis=1).astype(np.float32)
+        nst = steps_first if r == 0 else steps
+        for s in range(nst):
+            lr_k = lr * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * s / nst)))
+            net.train_step(x3, yt, lr=float(lr_k))
+        pred = np.asarray(net.forward(G3))
+        order = np.argsort(-pred)
+        chosen = []
+        for i in order:
+            p = G[i]
+            if np.all(np.any(np.abs(X - p) > min_sep, axis=1)) and \
+                    all(np.any(np.abs(c - p) > min_sep) for c in chosen):
+                chosen.append(p)
+                if len(chosen) == per_round:
+                    break
+        if not chosen:
+            break
+        C = np.array(chosen)
+        fc = np.asarray(obj(C), dtype=np.float64)
+        improved = fc.max() > F.max() + 0.05
+        X = np.concatenate([X, C])
+        F = np.concatenate([F, fc])
+        if log:
+            log(f"[mle] surrogate round {r + 1}: {len(C)} proposals, best proposal {fc.max():.3f}, "
+                f"best {F.max():.3f}, {obj.evals} exact evals")
+        stall = 0 if improved else stall + 1
+        if stall >= 2:
+            break
+    b = int(np.argmax(F))
+    return obj, X[b], float(F[b]), net
+
+
 def train_surrogate(tree: mra.Tree, n_train=2048, seed=5, steps=3000, lr=3e-3, family="matern", nu=1.5,
                     log=None):
     """Exact log-likelihoods at n_train Sobol points of the log box, then
@@ -213,38 +386,66 @@ def surrogate_proposal(net: mra.Mlp, k=48):
     return np.clip(np.array([g[1], g[2] - g[0]]), lo2, hi2)
 
 
-def run(tree: mra.Tree, family="matern", nu=1.5, n_train=2048, grid_k=32, seed=5, train_steps=3000, log=None):
-    """All three searches on one tree; evaluation counts to within 0.5 nats of
-    the best exact value any of them found."""
+def run(tree: mra.Tree, family="matern", nu=1.5, n_train=2048, grid_k=32, seed=5, train_steps=3000, log=None,
+        pretrained=True):
+    """All searches on one tree: exact evaluations, sequential exact calls and
+    evaluations to within 0.5 nats of the best exact value any of them found."""
     lo, hi = box2()
     width = hi - lo
+    t0 = time.time()
     g = ExactObjective(tree, family, nu)
     xg, fg = grid_search(g, grid_k, log=log)
+    tg = time.time() - t0
 
+    t0 = time.time()
     c = ExactObjective(tree, family, nu)
     xc, fc = nelder_mead(c, (lo + hi) / 2, width / 4)
+    tc = time.time() - t0
     if log:
-        log(f"[mle] local search without the surrogate: {c.evals} evals, best {fc:.3f}")
+        log(f"[mle] Nelder-Mead without the surrogate: {c.evals} evals, best {fc:.3f}")
 
-    net, n_tr = train_surrogate(tree, n_train, seed, train_steps, family=family, nu=nu, log=log)
-    s = ExactObjective(tree, family, nu)
-    x0 = surrogate_proposal(net)
-    f0 = float(s(x0)[0])
-    xs, fs = nelder_mead(s, x0, width / 32)
+    t0 = time.time()
+    b = ExactObjective(tree, family, nu)
+    xb, fb = trust_region(b, (lo + hi) / 2, 0.25)
+    tb = time.time() - t0
+    if log:
+        log(f"[mle] trust region (quadratic models): {b.evals} evals, best {fb:.3f}")
 
-    best = max(fg, fc, fs)
+    t0 = time.time()
+    q, xq, fq, _ = surrogate_sequential(tree, family, nu, seed=seed, log=log)
+    tq = time.time() - t0
+
+    found = [fg, fc, fb, fq]
+    res_p = None
+    if pretrained:
+        net, n_tr = train_surrogate(tree, n_train, seed, train_steps, family=family, nu=nu, log=log)
+        s = ExactObjective(tree, family, nu)
+        x0 = surrogate_proposal(net)
+        f0 = float(s(x0)[0])
+        xs, fs = nelder_mead(s, x0, width / 32)
+        found.append(fs)
+        res_p = {"train_evals": n_tr, "search_evals": s.evals, "total_evals": n_tr + s.evals,
+                 "proposal_loglik": f0, "loglik": fs, "beta": math.exp(xs[0]), "lam": math.exp(xs[1])}
+
+    best = max(found)
     target = best - 0.5
+
+    def entry(o, x, f, wall):
+        return {"evals": o.evals, "calls": o.calls, "evals_to_mle": o.evals_to_reach(target), "loglik": f,
+                "beta": math.exp(x[0]), "lam": math.exp(x[1]), "alpha": o.alpha_hat(x), "wall_s": wall}
+
     res = {
         "best_loglik": best,
-        "grid": {"evals": g.evals, "evals_to_mle": g.evals if fg >= target else None, "loglik": fg,
-                 "beta": math.exp(xg[0]), "lam": math.exp(xg[1]), "alpha": g.alpha_hat(xg)},
-        "local": {"evals": c.evals, "evals_to_mle": c.evals_to_reach(target), "loglik": fc,
-                    "beta": math.exp(xc[0]), "lam": math.exp(xc[1])},
-        "surrogate": {"train_evals": n_tr, "search_evals": s.evals, "evals_to_mle": s.evals_to_reach(target),
-                      "proposal_loglik": f0, "loglik": fs, "beta": math.exp(xs[0]), "lam": math.exp(xs[1]),
-                      "proposal_beta": math.exp(x0[0]), "proposal_lam": math.exp(x0[1])},
+        "grid": entry(g, xg, fg, tg),
+        "local": entry(c, xc, fc, tc),
+        "trust_region": entry(b, xb, fb, tb),
+        "surrogate": entry(q, xq, fq, tq),
     }
+    if res_p is not None:
+        res_p["evals_to_mle"] = s.evals_to_reach(target)
+        res["surrogate_pretrained"] = res_p
     if log:
-        log(f"[mle] grid {grid_k}x{grid_k}: {g.evals} evals, best {fg:.3f}; local search: {c.evals} evals, best {fc:.3f}; "
-            f"surrogate: proposal {f0:.3f}, {s.evals} search evals, best {fs:.3f}")
+        log(f"[mle] grid {grid_k}x{grid_k}: {g.evals} evals, best {fg:.3f}; Nelder-Mead {c.evals} evals "
+            f"({c.calls} calls), best {fc:.3f}; trust region {b.evals} evals ({b.calls} calls), best {fb:.3f}; "
+            f"surrogate {q.evals} evals ({q.calls} calls), best {fq:.3f}")
     return res

@@ -26,7 +26,7 @@ MRA_FOLD_FACTOR = 1 << 5
 EXPORTED = ["mra_build_tree", "mra_loglik", "mra_loglik_terms", "mra_loglik_status", "mra_loglik_noalloc",
             "mra_predict", "mra_free_tree", "mra_last_error",
             "mra_tree_info", "mra_tree_arrays", "mra_profile_enable", "mra_profile_read",
-            "mra_autotune", "mra_set_plan",
+            "mra_autotune", "mra_set_plan", "mra_bench_mfma_f64",
             "mra_mlp_create", "mra_mlp_set_scaling", "mra_mlp_forward", "mra_mlp_loss_grad",
             "mra_mlp_train_step", "mra_mlp_get_params", "mra_mlp_free"]
 MLP_WIDTH = 128
@@ -91,6 +91,8 @@ def load_library(path: str = LIB_PATH):
     L.mra_autotune.restype = C.c_int
     L.mra_set_plan.argtypes = [vp, vp, C.c_int]
     L.mra_set_plan.restype = C.c_int
+    L.mra_bench_mfma_f64.argtypes = [i64, C.POINTER(C.c_double)]
+    L.mra_bench_mfma_f64.restype = C.c_int
     f32 = C.c_float
     L.mra_mlp_create.argtypes = [vp, C.POINTER(vp)]
     L.mra_mlp_create.restype = C.c_int
@@ -157,6 +159,13 @@ def profile_read():
     _check(_lib.mra_profile_read(buf, cap, C.byref(cnt)))
     return [dict(name=buf[i].name.decode(), level=buf[i].level, launches=buf[i].launches, ms=buf[i].ms,
                  flops=buf[i].flops) for i in range(min(cnt.value, cap))]
+
+
+def mfma_peak_tflops(iters: int = 4096) -> float:
+    """Measured FP64 matrix-core rate of the device (mra_bench_mfma_f64)."""
+    v = C.c_double()
+    _check(_lib.mra_bench_mfma_f64(int(iters), C.byref(v)))
+    return v.value
 
 
 def family_code(family: str):

@@ -15,7 +15,7 @@ def _declared():
     for h in sorted(os.listdir(inc)):
         if h.endswith(".h"):
             src = re.sub(r"/\*.*?\*/", "", open(os.path.join(inc, h)).read(), flags=re.S)
-            names.update(re.findall(r"\b(mra_[a-z_]+)\s*\(", src))
+            names.update(re.findall(r"\b(mra_[a-z0-9_]+)\s*\(", src))
     return sorted(names)
 
 

@@ -1,6 +1,15 @@
-"""The surrogate-guided MLE search against the plain grid and against the same
-search without the surrogate, on a reduced mixture workload (exact MRA judges
-every value)."""
+"""MLE searches on exact GPU evaluations (the exact MRA judges every value),
+on a reduced mixture workload (n = 2^14, M = 5, r = 64):
+  * the sequential surrogate design reaches the MLE (within 0.5 nats of the
+    best value any search found) with fewer exact evaluations in total,
+    training included, than the 32 x 32 grid;
+  * what the network gains over the method without it: the same accuracy
+    in fewer sequential exact calls than the derivative-free searches
+    (Nelder-Mead, trust region), each of which is a chain of one- or
+    two-point calls;
+  * the trust-region search (after Powell) on GPU values reaches the optimum
+    the same search reaches on the CPU oracle's values.
+"""
 import numpy as np
 import pytest
 
@@ -15,23 +24,58 @@ def result():
     from paper_1905_00141_amd import mle, mra, synth
     c = synth.config3(n=1 << 14, M=5, device="cuda")
     t = mra.Tree(c["x"], c["y"], c["z"], J=4, r=64, M=5, domain=c["domain"])
-    res = mle.run(t, n_train=512, train_steps=1500, log=print)
+    res = mle.run(t, pretrained=False, log=print)
     print(res)
     return res
 
 
 def test_surrogate_reaches_the_mle_in_fewer_exact_evals_than_the_grid(result):
     s, g = result["surrogate"], result["grid"]
-    assert s["evals_to_mle"] is not None
-    assert s["evals_to_mle"] < g["evals"]
     assert s["loglik"] >= result["best_loglik"] - 0.5
+    assert s["evals_to_mle"] is not None and s["evals"] < g["evals"]
 
 
-def test_surrogate_proposal_is_close(result):
-    # the network's maximum alone is already within a few nats of the MLE
+def test_surrogate_needs_fewer_sequential_calls_than_the_searches_without_it(result):
     s = result["surrogate"]
-    assert s["proposal_loglik"] >= result["best_loglik"] - 25.0, s
+    for k in ("local", "trust_region"):
+        assert s["calls"] < result[k]["calls"], (k, s["calls"], result[k]["calls"])
 
 
-def test_grid_is_within_its_resolution(result):
+def test_derivative_free_searches_reach_the_mle(result):
+    assert result["trust_region"]["loglik"] >= result["best_loglik"] - 0.5
     assert result["grid"]["loglik"] >= result["best_loglik"] - 5.0
+
+
+def test_trust_region_matches_the_oracle_driven_search():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import oracle as o
+    from paper_1905_00141_amd import mle, mra, synth
+    c = synth.small_case(91, 900, J=4, r=16, M=3, cluster=True, nu=1.5)
+    t = mra.Tree(c["x"], c["y"], c["z"], J=4, r=16, M=3)
+    ot = o.Tree(c["x"], c["y"], c["z"], J=4, r=16, M=3)
+    n = ot.n_used
+
+    class OracleProfiled:
+        def __init__(self):
+            self.evals, self.history, self.best, self.calls = 0, [], -np.inf, 0
+
+        def __call__(self, X):
+            X = np.atleast_2d(X)
+            f = np.empty(len(X))
+            for i, (lb, ll) in enumerate(X):
+                b, lam = np.exp(lb), np.exp(ll)
+                l1, l2 = ot.loglik(np.array([[1.0, b, lam], [2.0, b, 2.0 * lam]]), o.MATERN, 1.5)
+                k1 = -2 * l1 - n * np.log(2 * np.pi)
+                k2 = -2 * l2 - n * np.log(2 * np.pi) - n * np.log(2.0)
+                Q = 2.0 * (k1 - k2)
+                f[i] = -0.5 * (n * np.log(2 * np.pi) + (k1 - Q) + n * np.log(Q / n) + n)
+                self.evals += 1
+            return f
+
+    lo, hi = mle.box2()
+    xo, fo = mle.trust_region(OracleProfiled(), (lo + hi) / 2, 0.25, rho_end=1e-4)
+    xg, fg = mle.trust_region(mle.ExactObjective(t, "matern", 1.5), (lo + hi) / 2, 0.25, rho_end=1e-4)
+    print("oracle-driven", xo, fo, "gpu-driven", xg, fg)
+    assert abs(fg - fo) <= 1e-6 * abs(fo) and np.allclose(xg, xo, atol=1e-3)
