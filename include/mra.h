@@ -65,7 +65,11 @@ typedef struct mra_tree mra_tree;
  *             r_hat = that product knots are placed.  The library supports
  *             r_hat <= 64 (MRA_EINVAL beyond).
  *   M       : number of levels, >= 1.  The finest level holds the observations
- *             as its knots.
+ *             as its knots.  M <= 0 selects the default of Sec. 2.2: the M for
+ *             which the finest level's average count per region, n_obs /
+ *             J^(M-1), is closest on a log scale to r_hat (n_obs: inputs with
+ *             a value; M = 1 when n_obs <= r_hat), i.e.
+ *             M = 1 + max(0, floor(log_J(n_obs / r_hat) + 1/2)).
  *   offset  : knot offset as a fraction of the region side; <= 0 selects the
  *             default e/100 (Sec. 1.2, Appendix A).
  *   domain4 : {xmin, xmax, ymin, ymax} of the root region, used verbatim, or
@@ -119,6 +123,20 @@ int mra_loglik(const mra_tree *tree, int family, double nu, const double *theta,
  */
 int mra_loglik_terms(const mra_tree *tree, int family, double nu, const double *theta, int64_t B,
                      double *loglik, double *logdet, double *quad, void *stream);
+
+/*
+ * Per-level breakdown of the log-determinant term, to localise a
+ * disagreement with another implementation: level_logdet[b * M + (m - 1)] is
+ * the sum over the level-m regions of their log-determinant contributions
+ * (finest level: log det of each region's finest-level covariance plus nugget;
+ * above it: log det (B + At) - log det B of each fold, in the notation of the
+ * prior/posterior recursion), for m = 1 .. M; the M values add up to
+ * log det(Sigma_MRA + tau I).  loglik as for mra_loglik.  Memory spaces,
+ * stream and errors as for mra_loglik (host outputs: the call is synchronous);
+ * these calls are not graph-captured.
+ */
+int mra_loglik_levels(const mra_tree *tree, int family, double nu, const double *theta, int64_t B,
+                      double *loglik, double *level_logdet, void *stream);
 
 /*
  * mra_loglik for callers that cannot allocate device memory (code under HIP

@@ -418,6 +418,7 @@ typedef struct {
     int p;
     anc_t anc[O_MAXLEV + 1]; /* anc[l] = ancestor at level l on the current path */
     double level_sum[O_MAXLEV];
+    double level_logdet[O_MAXLEV]; /* the log-determinant terms d alone, per level */
     int status;
     int64_t bad_region;
     pred_t *pred;            /* NULL for the likelihood */
@@ -676,6 +677,7 @@ static void visit(rctx *ctx, int m, int64_t k, double *A, double *w, double *du)
         for (int a = 0; a < np; a++) u += pz[a] * X[(int64_t)a * wd + q];
         *du = d + u;
         ctx->level_sum[M - 1] += d + u;
+        ctx->level_logdet[M - 1] += d;
         free(X);
         if (ctx->pred) leaf_predict(ctx, k, np, px, py, pz, B, S);
     leaf_done:
@@ -741,6 +743,7 @@ static void visit(rctx *ctx, int m, int64_t k, double *A, double *w, double *du)
             }
             *du = du_sub + d + u;
             ctx->level_sum[m - 1] += d + u;
+            ctx->level_logdet[m - 1] += d;
             free(Y);
         }
         free(Ki);
@@ -781,6 +784,10 @@ int oracle_mra_subtree(const otree *t, int family, double nu, const double *thet
 
 static const double LOG2PI = 1.8378770664093454835606594728112;
 
+/* Destination of the per-level log-determinant sums while
+ * oracle_mra_level_logdets runs (NULL otherwise). */
+static double *g_level_logdet = NULL;
+
 /* Log-likelihood of theta[b] = (alpha, beta, tau) for b < B.  level_sums, if
  * given, receives per theta the sum of d + u over each level (M values). */
 int oracle_mra_loglik(const otree *t, int family, double nu, const double *theta, int64_t B,
@@ -812,9 +819,24 @@ int oracle_mra_loglik(const otree *t, int family, double nu, const double *theta
         loglik[b] = -0.5 * ((double)t->n_used * LOG2PI + du);
         if (level_sums)
             for (int m = 0; m < t->M; m++) level_sums[b * t->M + m] = ctx->level_sum[m];
+        if (g_level_logdet)
+            for (int m = 0; m < t->M; m++) g_level_logdet[b * t->M + m] = ctx->level_logdet[m];
         free(ctx);
     }
     return O_OK;
+}
+
+/* Per theta and level m = 1..M, the sum over the level's regions of their
+ * log-determinant term d (leaves: log det Sigma_R; folds: log det Kt^{-1} -
+ * log det B^m_R); the M values add up to log det(Sigma_MRA + tau I).  out is
+ * B x M.  Not thread-safe (it routes the sums through a static pointer). */
+int oracle_mra_level_logdets(const otree *t, int family, double nu, const double *theta, int64_t B, double *out) {
+    double *ll = malloc(sizeof(double) * (size_t)(B > 0 ? B : 1));
+    g_level_logdet = out;
+    int rc = oracle_mra_loglik(t, family, nu, theta, B, ll, NULL);
+    g_level_logdet = NULL;
+    free(ll);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -140,6 +140,16 @@ class Tree:
                                        None if ls is None else _p(ls)))
         return (out, ls) if level_sums else out
 
+    def level_logdets(self, theta, family=MATERN, nu=0.5):
+        """(B, M): per level, the sum of the regions' log-determinant terms."""
+        th = np.ascontiguousarray(np.atleast_2d(theta), dtype=np.float64)
+        out = np.empty((th.shape[0], self.M))
+        L = lib()
+        L.oracle_mra_level_logdets.argtypes = [C.c_void_p, C.c_int, C.c_double, C.POINTER(C.c_double), C.c_int64,
+                                               C.POINTER(C.c_double)]
+        _check(L.oracle_mra_level_logdets(self._h, family, float(nu), _p(th), th.shape[0], _p(out)))
+        return out
+
     def dense_sigma(self, theta, family=MATERN, nu=0.5):
         th = np.ascontiguousarray(theta, dtype=np.float64)
         S = np.empty((self.n_used, self.n_used))

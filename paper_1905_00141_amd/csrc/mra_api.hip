@@ -472,6 +472,19 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
             return fail(MRA_EDEVICE, "copy of device inputs failed");
         px = hx.data(); py = hy.data(); pz = hz.data();
     }
+    if (M <= 0) {
+        // NUM_LEVELS_M "default" (Sec. 2.2): the finest level's average count
+        // per region closest, on a log scale, to the knots per coarser region
+        if (J != 2 && J != 4) return fail(MRA_EINVAL, "J must be 2 or 4");
+        if (r < 1) return fail(MRA_EINVAL, "r must be >= 1");
+        int64_t nobs = 0;
+        for (int64_t i = 0; i < n; ++i) nobs += std::isnan(pz[i]) ? 0 : 1;
+        int nx = 1;
+        while (int64_t(nx) * nx < r) ++nx;
+        const int64_t rhat = int64_t(nx) * (r / nx);
+        M = 1;
+        if (nobs > rhat) M = 1 + std::max(0, int(std::floor(std::log(double(nobs) / double(rhat)) / std::log(double(J)) + 0.5)));
+    }
     auto* t = new mra_tree();
     t->flags = flags;
     (void)hipGetDevice(&t->device);
@@ -782,7 +795,8 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
 // theta (the per-theta buffers of a.vst, a.F, a.gram, a.dval hold Bc theta;
 // nslot workgroup slots of a.scratch).
 static hipError_t enqueue_loglik(const mra_tree* t, int64_t Bc, int64_t nslot, KArgs a, const double* d_th,
-                                 double* d_out, double* d_ld, double* d_q, int* status, int64_t B, hipStream_t st) {
+                                 double* d_out, double* d_ld, double* d_q, int* status, int64_t B, hipStream_t st,
+                                 double* d_lev = nullptr) {
     const HostTree& h = t->h;
     const Plan& pl = t->lik;
     hipError_t e;
@@ -795,6 +809,7 @@ static hipError_t enqueue_loglik(const mra_tree* t, int64_t Bc, int64_t nslot, K
         a.out = d_out + b0;
         a.out_ld = d_ld ? d_ld + b0 : nullptr;
         a.out_q = d_q ? d_q + b0 : nullptr;
+        a.out_lev = d_lev ? d_lev + b0 * h.M : nullptr;
         if ((e = launch_fill(a.dval, int64_t(nb) * a.d_stride, 0.0, st))) return e;
         if ((e = enqueue_prior(t, pl, a, nb, st))) return e;
         if ((e = enqueue_leaves(t, pl, a, nb, nslot, st))) return e;
@@ -813,7 +828,7 @@ static bool graphs_enabled() {
 }
 
 static int loglik_impl(const mra_tree* t, int family, double nu, const double* theta, int64_t B, double* loglik,
-                       double* logdet, double* quad, void* stream) {
+                       double* logdet, double* quad, void* stream, double* levels = nullptr) {
     if (!t || !theta || !loglik || B < 1) return fail(MRA_EINVAL, "NULL argument or B < 1");
     int smooth = 0;
     int rc = smooth_of(family, nu, &smooth);
@@ -821,8 +836,9 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
     const HostTree& h = t->h;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     const bool dev = is_device_ptr(theta);
-    if (dev != is_device_ptr(loglik) || (logdet && dev != is_device_ptr(logdet)) || (quad && dev != is_device_ptr(quad)))
-        return fail(MRA_EINVAL, "theta, loglik, logdet and quad must be in the same memory space");
+    if (dev != is_device_ptr(loglik) || (logdet && dev != is_device_ptr(logdet)) || (quad && dev != is_device_ptr(quad)) ||
+        (levels && dev != is_device_ptr(levels)))
+        return fail(MRA_EINVAL, "theta and the outputs must be in the same memory space");
     const bool zn = (t->flags & MRA_ALLOW_ZERO_NUGGET) != 0;
     if (!dev)
         for (int64_t b = 0; b < B; ++b)
@@ -839,6 +855,13 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
     double* d_out = dev ? loglik : w.out;
     double* d_ld = logdet ? (dev ? logdet : w.ld) : nullptr;
     double* d_q = quad ? (dev ? quad : w.q) : nullptr;
+    double* d_lev = nullptr;
+    if (levels && !dev) {
+        if (hipMallocAsync(reinterpret_cast<void**>(&d_lev), size_t(B) * h.M * 8, st) != hipSuccess)
+            return fail(MRA_ENOMEM, "device allocation of the per-level sums failed");
+    } else if (levels) {
+        d_lev = levels;
+    }
     std::vector<int> hstatus;
     KArgs a = base_args(t, t->lik, smooth);
     a.vst = w.vst; a.F = w.F; a.gram = w.gram; a.dval = w.dval;
@@ -849,7 +872,7 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
         profiling = g_prof_on;
     }
     if (!dev) HIPCHK(hipMemcpyAsync(d_th, theta, 3 * B * 8, hipMemcpyHostToDevice, st));
-    if (dev && st != nullptr && !profiling && graphs_enabled()) {
+    if (dev && st != nullptr && !profiling && graphs_enabled() && !levels) {
         // a repeated evaluation on the same buffers replays one captured graph
         const auto key = std::make_tuple(static_cast<const void*>(theta), static_cast<void*>(loglik),
                                          static_cast<void*>(logdet), static_cast<void*>(quad), B, smooth,
@@ -870,7 +893,7 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
         }
         HIPCHK(hipGraphLaunch(it->second, st));
     } else {
-        HIPCHK(enqueue_loglik(t, w.Bc, w.nslot, a, d_th, d_out, d_ld, d_q, w.status, B, st));
+        HIPCHK(enqueue_loglik(t, w.Bc, w.nslot, a, d_th, d_out, d_ld, d_q, w.status, B, st, d_lev));
     }
     (void)hipEventRecord(w.done, st);
     w.last = st;
@@ -881,12 +904,14 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
         HIPCHK(hipMemcpyAsync(loglik, d_out, B * 8, hipMemcpyDeviceToHost, st));
         if (logdet) HIPCHK(hipMemcpyAsync(logdet, d_ld, B * 8, hipMemcpyDeviceToHost, st));
         if (quad) HIPCHK(hipMemcpyAsync(quad, d_q, B * 8, hipMemcpyDeviceToHost, st));
+        if (levels) HIPCHK(hipMemcpyAsync(levels, d_lev, size_t(B) * h.M * 8, hipMemcpyDeviceToHost, st));
         hstatus.resize(B);
         HIPCHK(hipMemcpyAsync(hstatus.data(), w.status, B * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         rc = status_message(h, hstatus.data(), B);
     }
 done:
+    if (d_lev && d_lev != levels) (void)hipFreeAsync(d_lev, st);
     return rc;
 }
 
@@ -917,6 +942,12 @@ extern "C" int mra_loglik(const mra_tree* t, int family, double nu, const double
 extern "C" int mra_loglik_terms(const mra_tree* t, int family, double nu, const double* theta, int64_t B,
                                 double* loglik, double* logdet, double* quad, void* stream) {
     return loglik_impl(t, family, nu, theta, B, loglik, logdet, quad, stream);
+}
+
+extern "C" int mra_loglik_levels(const mra_tree* t, int family, double nu, const double* theta, int64_t B,
+                                 double* loglik, double* level_logdet, void* stream) {
+    if (!level_logdet) return fail(MRA_EINVAL, "level_logdet is NULL");
+    return loglik_impl(t, family, nu, theta, B, loglik, nullptr, nullptr, stream, level_logdet);
 }
 
 // ------------------------------------------- evaluation without allocation

@@ -461,6 +461,21 @@ __global__ void __launch_bounds__(NT) k_final(KArgs a, int64_t nreg, int root_gr
     }
     const double dsum = red[0];
     __syncthreads();
+    // optional per-level sums (same fixed order within each level)
+    if (a.out_lev) {
+        for (int m = 1; m <= a.M; ++m) {
+            double sl = 0.0;
+            for (int64_t g = a.lvl[m - 1] + threadIdx.x; g < a.lvl[m]; g += NT) sl += d[g];
+            red[threadIdx.x] = sl;
+            __syncthreads();
+            for (int w = NT / 2; w > 0; w /= 2) {
+                if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) a.out_lev[int64_t(th) * a.M + (m - 1)] = (a.status[th] != 0) ? __builtin_nan("") : red[0];
+            __syncthreads();
+        }
+    }
     double q = 0.0;
     if (root_gram) {
         const int D = a.P + 1;

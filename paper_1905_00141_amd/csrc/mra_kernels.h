@@ -52,6 +52,7 @@ struct KArgs {
     double* out;              // final: loglik per theta
     double* out_ld;           // final (optional): sum of log-determinants per theta
     double* out_q;            // final (optional): quadratic form per theta
+    double* out_lev;          // final (optional): per theta, M sums of log-determinants, one per level
     double n_used;
     int zero_nugget;          // 1: tau = 0 is a valid nugget
     // prediction (one theta): points grouped by leaf

@@ -23,7 +23,8 @@ MRA_ALLOW_ZERO_NUGGET = 1 << 2
 MRA_FOLD_GRAM = 1 << 4
 MRA_FOLD_FACTOR = 1 << 5
 
-EXPORTED = ["mra_build_tree", "mra_loglik", "mra_loglik_terms", "mra_loglik_status", "mra_loglik_noalloc",
+EXPORTED = ["mra_build_tree", "mra_loglik", "mra_loglik_terms", "mra_loglik_levels", "mra_loglik_status",
+            "mra_loglik_noalloc",
             "mra_predict", "mra_free_tree", "mra_last_error",
             "mra_tree_info", "mra_tree_arrays", "mra_profile_enable", "mra_profile_read",
             "mra_autotune", "mra_set_plan", "mra_bench_mfma_f64",
@@ -69,6 +70,8 @@ def load_library(path: str = LIB_PATH):
     L.mra_loglik.restype = C.c_int
     L.mra_loglik_terms.argtypes = [vp, C.c_int, C.c_double, pd, i64, pd, pd, pd, vp]
     L.mra_loglik_terms.restype = C.c_int
+    L.mra_loglik_levels.argtypes = [vp, C.c_int, C.c_double, pd, i64, pd, pd, vp]
+    L.mra_loglik_levels.restype = C.c_int
     L.mra_loglik_noalloc.argtypes = [vp, C.c_int, C.c_double, pd, i64, pd, vp]
     L.mra_loglik_noalloc.restype = C.c_int
     L.mra_loglik_status.argtypes = [vp]
@@ -228,6 +231,14 @@ class Tree:
         _check(_lib.mra_loglik(self._h, family_code(family), float(nu), _ptr(th), B, _ptr(res),
                                _stream_ptr(stream)))
         return res
+
+    def level_logdets(self, theta, family="matern", nu=0.5):
+        """(loglik (B,), per-level log-determinant sums (B, M)); host arrays."""
+        th = np.ascontiguousarray(np.atleast_2d(theta), dtype=np.float64)
+        ll, lev = np.empty(th.shape[0]), np.empty((th.shape[0], self.M))
+        _check(_lib.mra_loglik_levels(self._h, family_code(family), float(nu), th.ctypes.data, th.shape[0],
+                                      ll.ctypes.data, lev.ctypes.data, None))
+        return ll, lev
 
     def loglik_noalloc(self, theta, out, family="matern", nu=0.5, stream=None):
         """mra_loglik_noalloc: device theta (B, 3) and device out (B,), no allocation."""

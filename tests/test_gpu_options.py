@@ -114,3 +114,30 @@ def test_plan_with_falling_threshold(mra, oracle):
         t.set_plan(fm, sm)
         got = t.loglik(THETAS, "matern", 1.5)
         assert np.all(_rel(got, ref) <= RTOL), (fm, sm, _rel(got, ref))
+
+
+def test_default_levels_data_file_and_prediction_modes(mra, oracle, tmp_path):
+    """NUM_LEVELS_M 'default' (M = 0), a tree built from the paper's data
+    file layout, and kriging at the 'N' locations (the file's NaN values)."""
+    from paper_1905_00141_amd import datafile as df
+    from paper_1905_00141_amd import synth
+    c = synth.small_case(71, 3000, J=4, r=16, M=3, cluster=True)
+    z = c["z"].copy()
+    z[::10] = np.nan
+    p = tmp_path / "data.bin"
+    df.write_data_file(p, c["x"], c["y"], z)
+    x, y, zz = df.read_data_file(p)
+    t = mra.Tree(x, y, zz, J=4, r=16, M=0, domain=[0, 1, 0, 1])
+    M = df.default_levels(int(np.count_nonzero(~np.isnan(zz))), 4, 16)
+    assert t.info["M"] == M
+    o = oracle.Tree(x, y, zz, J=4, r=16, M=M, domain=[0, 1, 0, 1])
+    got = t.loglik(THETAS, "matern", 0.5)
+    assert np.all(_rel(got, o.loglik(THETAS, oracle.MATERN, 0.5)) <= RTOL)
+    px, py = df.prediction_locations("N", x, y, zz)
+    assert len(px) == 300
+    m, v = t.predict((1.0, 0.1, 0.02), px, py, "matern", 0.5)
+    mo, vo = o.predict((1.0, 0.1, 0.02), px, py, oracle.MATERN, 0.5)
+    assert np.abs(m - mo).max() <= 1e-10 * (np.abs(mo).max() + 1) and np.abs(v - vo).max() <= 1e-10
+    q = tmp_path / "pred.bin"
+    df.write_prediction_file(q, px, py, m, v)
+    assert np.array_equal(df.read_prediction_file(q)[2], m)

@@ -81,3 +81,19 @@ def test_structure_loglik_matches_oracle(mra, case, plan):
         assert any(n == "k_gram_tile2" for n, _ in ran)
     for _ in range(3):
         assert np.array_equal(t.loglik(THETAS, "matern", 1.5), got)
+
+
+def test_per_level_log_determinants_match_the_oracle(mra, case):
+    """The per-level breakdown of the log-determinant (mra_loglik_levels)
+    against the oracle's, level by level, on the same tree: bar 1e-10 of the
+    total log-determinant's magnitude per level."""
+    from oracle import oracle as o
+    th = THETAS[1:2]
+    t = mra.Tree(case["x"], case["y"], case["z"], J=4, r=R, M=M, domain=[0, 1, 0, 1])
+    ll, lev = t.level_logdets(th, "matern", 1.5)
+    ot = o.Tree(case["x"], case["y"], case["z"], J=4, r=R, M=M, domain=[0, 1, 0, 1])
+    ref = ot.level_logdets(th, o.MATERN, 1.5)
+    scale = np.abs(ref).sum()
+    print("levels gpu", lev, "oracle", ref)
+    assert np.all(np.abs(lev - ref) <= 1e-10 * scale), np.abs(lev - ref) / scale
+    assert abs(ll[0] - case["ref"][1]) <= 1e-10 * abs(case["ref"][1])

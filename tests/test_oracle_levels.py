@@ -203,3 +203,40 @@ def test_zero_nugget_M1_is_the_noise_free_gaussian():
     K = _cov_np(_dist(a["x"], a["y"], a["x"], a["y"]), th[0], th[1], 0.5)
     ref = multivariate_normal(mean=np.zeros(n), cov=K).logpdf(a["z"])
     assert abs(t.loglik(th, MATERN, 0.5)[0] - ref) <= 1e-9 * abs(ref)
+
+
+# ---------------------------------------------------- per-level log-determinants
+
+@pytest.mark.parametrize("J,M,r,n,cluster,nu", [(4, 3, 16, 600, True, 0.5), (4, 4, 9, 800, False, 1.5),
+                                                (2, 5, 4, 500, True, 1.5)])
+def test_level_logdets_add_up_to_the_dense_log_determinant(J, M, r, n, cluster, nu):
+    """The per-level log-determinant terms add up to log det(Sigma_MRA + tau I),
+    computed by NumPy from the oracle's definitional dense covariance."""
+    c = synth.small_case(700 + n, n, J=J, r=r, M=M, cluster=cluster, nu=nu)
+    t = Tree(c["x"], c["y"], c["z"], J=J, r=r, M=M)
+    th = (1.3, 0.09, 0.02)
+    lev = t.level_logdets(th, MATERN, nu)[0]
+    S = t.dense_sigma(th, MATERN, nu) + th[2] * np.eye(t.n_used)
+    sign, ld = np.linalg.slogdet(S)
+    assert sign > 0 and abs(lev.sum() - ld) <= 1e-10 * abs(ld)
+
+
+def test_level_logdets_two_level_closed_form():
+    """M = 2: the finest level holds the leaves' log det(C_2(S,S) + tau I)."""
+    rng = np.random.default_rng(29)
+    n = 250
+    x, y, z = rng.random(n), rng.random(n), rng.standard_normal(n)
+    dom = [0.0, 1.0, 0.0, 1.0]
+    th = (0.8, 0.12, 0.04)
+    t = Tree(x, y, z, J=4, r=9, M=2, domain=dom)
+    a = t.arrays()
+    sx, sy = a["x"], a["y"]
+    qx, qy = _grid_knots_np(dom, 9)
+    Cqq = _cov_np(_dist(qx, qy, qx, qy), th[0], th[1], 1.5)
+    Csq = _cov_np(_dist(sx, sy, qx, qy), th[0], th[1], 1.5)
+    R = _cov_np(_dist(sx, sy, sx, sy), th[0], th[1], 1.5) - Csq @ np.linalg.solve(Cqq, Csq.T)
+    leaf = (sx >= 0.5).astype(int) + 2 * (sy >= 0.5).astype(int)
+    want = sum(np.linalg.slogdet(R[np.ix_(leaf == k, leaf == k)] + th[2] * np.eye(int((leaf == k).sum())))[1]
+               for k in range(4) if (leaf == k).any())
+    lev = t.level_logdets(th, MATERN, 1.5)[0]
+    assert abs(lev[1] - want) <= 1e-10 * abs(want)
