@@ -40,9 +40,14 @@ typedef struct mra_tree mra_tree;
 /* covariance families; distance t = |a - b| / range (Euclidean, in the plane)
  *   MRA_EXP           : sill * exp(-t)                  (the paper's exponential)
  *   MRA_MATERN nu=0.5 : sill * exp(-t)
- *   MRA_MATERN nu=1.5 : sill * (1 + t) * exp(-t)                                  */
+ *   MRA_MATERN nu=1.5 : sill * (1 + t) * exp(-t)
+ *   MRA_MATERN nu=2.5 : sill * (1 + t + t^2/3) * exp(-t)
+ *   MRA_GAUSS         : sill * exp(-t^2)   (nu ignored; its knot matrices become
+ *                       singular in FP64 once the knot spacing is well below the
+ *                       range, which mra_loglik reports as MRA_ENOTPD)           */
 #define MRA_EXP 0
 #define MRA_MATERN 1
+#define MRA_GAUSS 2
 
 /* mra_build_tree flags */
 #define MRA_DEVICE_PTRS (1u << 0)  /* x, y, z are device pointers (else host) */

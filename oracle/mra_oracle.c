@@ -309,18 +309,21 @@ int oracle_tree_arrays(const otree *t, double *x, double *y, double *z, int64_t 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Covariance.  Exponential (the only family in the paper's code, Sec. 2.2)   */
-/* and Matern nu = 3/2, both as functions of t = distance / range:            */
-/*   nu = 1/2 : alpha * exp(-t);   nu = 3/2 : alpha * (1 + t) * exp(-t).       */
+/* Covariance.  Exponential (the only family in the paper's code, Sec. 2.2), */
+/* Matern nu = 3/2 and 5/2, and Gaussian, as functions of t = distance/range: */
+/*   nu = 1/2 : alpha * exp(-t);   nu = 3/2 : alpha * (1 + t) * exp(-t);       */
+/*   nu = 5/2 : alpha * (1 + t + t^2/3) * exp(-t);  Gaussian: alpha exp(-t^2). */
 /* Euclidean distance in the (x, y) plane; the nugget is not part of C.       */
 /* ------------------------------------------------------------------------ */
-typedef struct { double alpha, beta, tau; int smooth; } cpar; /* smooth: 0 -> 1/2, 1 -> 3/2 */
+typedef struct { double alpha, beta, tau; int smooth; } cpar; /* smooth: 0 -> 1/2, 1 -> 3/2, 2 -> 5/2, 3 -> Gaussian */
 
 static double cov(double ax, double ay, double bx, double by, const cpar *c) {
     double dx = ax - bx, dy = ay - by;
     double t = sqrt(dx * dx + dy * dy) / c->beta;
-    if (c->smooth) return c->alpha * (1.0 + t) * exp(-t);
-    return c->alpha * exp(-t);
+    if (c->smooth == 3) return c->alpha * exp(-t * t);            /* Gaussian */
+    if (c->smooth == 2) return c->alpha * (1.0 + t + t * t / 3.0) * exp(-t); /* Matern 5/2 */
+    if (c->smooth == 1) return c->alpha * (1.0 + t) * exp(-t);    /* Matern 3/2 */
+    return c->alpha * exp(-t);                                    /* exponential, Matern 1/2 */
 }
 
 static int make_par(int family, double nu, const double *th, cpar *c) {
@@ -329,6 +332,8 @@ static int make_par(int family, double nu, const double *th, cpar *c) {
     if (family == 0) { c->smooth = 0; return O_OK; }
     if (family == 1 && nu == 0.5) { c->smooth = 0; return O_OK; }
     if (family == 1 && nu == 1.5) { c->smooth = 1; return O_OK; }
+    if (family == 1 && nu == 2.5) { c->smooth = 2; return O_OK; }
+    if (family == 2) { c->smooth = 3; return O_OK; }
     return fail(O_EINVAL, "unsupported covariance family / nu");
 }
 

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mra_oracle.c")
 _LIB = os.path.join(_HERE, "libmra_oracle.so")
 
-EXP, MATERN = 0, 1
+EXP, MATERN, GAUSS = 0, 1, 2
 ELIM_DUPLICATES = 1 << 1
 ALLOW_ZERO_NUGGET = 1 << 2
 

@@ -23,7 +23,7 @@ ARCH = "gfx950"
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I" + INCLUDE, "-I" + CSRC]
-HIP_SOURCES = ["mra_chain.hip", "mra_finish.hip", "mra_gram.hip", "mra_pred.hip", "mra_api.hip", "mra_mlp.hip", "mra_bench.hip"]
+HIP_SOURCES = ["mra_chain.hip", "mra_finish.hip", "mra_gram.hip", "mra_pred.hip", "mra_api.hip", "mra_mlp.hip", "mra_bench.hip", "mra_tree_gpu.hip"]
 HOST_SOURCES = ["mra_tree.cpp"]
 
 

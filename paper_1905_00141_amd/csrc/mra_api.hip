@@ -159,6 +159,7 @@ struct mra_tree {
     int device = 0;
     uint32_t flags = 0;
     double *d_x = nullptr, *d_y = nullptr, *d_z = nullptr, *d_box = nullptr;
+    int64_t* d_orig = nullptr;  // input index of each grouped observation (GPU-built trees)
     int64_t *d_obs_lo = nullptr, *d_obs_hi = nullptr;
     int WF = 1, WFs = 4;
     Plan lik;  // plan of the likelihood
@@ -462,9 +463,13 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
     if (n > (int64_t(1) << 31) - 1) return fail(MRA_EINVAL, "n must fit in 31 bits");
     int rc = check_device();
     if (rc) return rc;
+    // the partition is built on the GPU, except with duplicate elimination
+    // (host build; MRA_HOST_TREE=1 in the environment also selects it)
+    const char* ht = std::getenv("MRA_HOST_TREE");
+    const bool on_gpu = !(flags & MRA_ELIM_DUPLICATES) && !(ht && *ht == '1');
     std::vector<double> hx, hy, hz;
     const double *px = x, *py = y, *pz = z;
-    if (flags & MRA_DEVICE_PTRS) {
+    if ((flags & MRA_DEVICE_PTRS) && (!on_gpu || M <= 0)) {
         hx.resize(n); hy.resize(n); hz.resize(n);
         if (n > 0 && (hipMemcpy(hx.data(), x, n * 8, hipMemcpyDeviceToHost) != hipSuccess ||
                       hipMemcpy(hy.data(), y, n * 8, hipMemcpyDeviceToHost) != hipSuccess ||
@@ -489,7 +494,27 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
     t->flags = flags;
     (void)hipGetDevice(&t->device);
     std::string err;
-    rc = build_host_tree(px, py, pz, n, J, r, M, offset, flags, domain4, t->h, err);
+    if (on_gpu) {
+        // device inputs: the caller's (MRA_DEVICE_PTRS) or a temporary copy
+        const double *dx = x, *dy = y, *dz = z;
+        double* up[3] = {nullptr, nullptr, nullptr};
+        if (!(flags & MRA_DEVICE_PTRS)) {
+            const double* src[3] = {x, y, z};
+            for (int c = 0; c < 3; ++c)
+                if (hipMalloc(reinterpret_cast<void**>(&up[c]), std::max<int64_t>(n, 1) * 8) != hipSuccess ||
+                    (n > 0 && hipMemcpy(up[c], src[c], n * 8, hipMemcpyHostToDevice) != hipSuccess)) {
+                    for (double* p : up) if (p) (void)hipFree(p);
+                    delete t;
+                    return fail(MRA_ENOMEM, "device copy of the inputs failed");
+                }
+            dx = up[0]; dy = up[1]; dz = up[2];
+        }
+        rc = build_device_tree(dx, dy, dz, n, J, r, M, offset, domain4, t->h, &t->d_x, &t->d_y, &t->d_z, &t->d_orig,
+                               err);
+        for (double* p : up) if (p) (void)hipFree(p);
+    } else {
+        rc = build_host_tree(px, py, pz, n, J, r, M, offset, flags, domain4, t->h, err);
+    }
     if (rc) { delete t; return fail(rc, err); }
     const HostTree& h = t->h;
     if (M - 1 > chain_lmax(h.P)) {
@@ -515,7 +540,7 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
         return fail(rc, err);
     }
     std::vector<int64_t> lo(h.obs_lo), hi(h.obs_hi);
-    if ((rc = upload(&t->d_x, h.x)) || (rc = upload(&t->d_y, h.y)) || (rc = upload(&t->d_z, h.z)) ||
+    if ((!on_gpu && ((rc = upload(&t->d_x, h.x)) || (rc = upload(&t->d_y, h.y)) || (rc = upload(&t->d_z, h.z)))) ||
         (rc = upload(&t->d_box, h.box)) || (rc = upload(&t->d_obs_lo, lo)) || (rc = upload(&t->d_obs_hi, hi))) {
         delete t;
         return fail(rc, "device allocation or copy failed while uploading the tree");
@@ -542,10 +567,18 @@ extern "C" int mra_tree_arrays(const mra_tree* t, double* x, double* y, double* 
     if (!t) return fail(MRA_EINVAL, "NULL tree");
     const HostTree& h = t->h;
     const size_t n = size_t(h.n_used);
-    if (x) std::memcpy(x, h.x.data(), n * 8);
-    if (y) std::memcpy(y, h.y.data(), n * 8);
-    if (z) std::memcpy(z, h.z.data(), n * 8);
-    if (orig) std::memcpy(orig, h.orig.data(), n * 8);
+    if (t->d_orig) {  // built on the GPU: the grouped observations live on the device
+        if ((x && n && hipMemcpy(x, t->d_x, n * 8, hipMemcpyDeviceToHost) != hipSuccess) ||
+            (y && n && hipMemcpy(y, t->d_y, n * 8, hipMemcpyDeviceToHost) != hipSuccess) ||
+            (z && n && hipMemcpy(z, t->d_z, n * 8, hipMemcpyDeviceToHost) != hipSuccess) ||
+            (orig && n && hipMemcpy(orig, t->d_orig, n * 8, hipMemcpyDeviceToHost) != hipSuccess))
+            return fail(MRA_EDEVICE, "copy of the tree's observations failed");
+    } else {
+        if (x) std::memcpy(x, h.x.data(), n * 8);
+        if (y) std::memcpy(y, h.y.data(), n * 8);
+        if (z) std::memcpy(z, h.z.data(), n * 8);
+        if (orig) std::memcpy(orig, h.orig.data(), n * 8);
+    }
     if (leaf_off) {
         const int64_t l0 = h.lvl_start[h.M - 1];
         for (int64_t k = 0; k < h.nleaf; ++k) leaf_off[k] = h.obs_lo[l0 + k];
@@ -558,7 +591,9 @@ static int smooth_of(int family, double nu, int* smooth) {
     if (family == MRA_EXP) { *smooth = 0; return MRA_OK; }
     if (family == MRA_MATERN && nu == 0.5) { *smooth = 0; return MRA_OK; }
     if (family == MRA_MATERN && nu == 1.5) { *smooth = 1; return MRA_OK; }
-    return fail(MRA_EINVAL, "family must be MRA_EXP or MRA_MATERN with nu 0.5 or 1.5");
+    if (family == MRA_MATERN && nu == 2.5) { *smooth = 2; return MRA_OK; }
+    if (family == MRA_GAUSS) { *smooth = 3; return MRA_OK; }
+    return fail(MRA_EINVAL, "family must be MRA_EXP, MRA_MATERN with nu 0.5, 1.5 or 2.5, or MRA_GAUSS");
 }
 
 static int region_level(const HostTree& h, int64_t g) {
@@ -741,7 +776,7 @@ mra_tree::~mra_tree() {
         static_cast<Workspace*>(ws)->release();
         delete static_cast<Workspace*>(ws);
     }
-    void* ps[] = {d_x, d_y, d_z, d_box, d_obs_lo, d_obs_hi};
+    void* ps[] = {d_x, d_y, d_z, d_box, d_obs_lo, d_obs_hi, d_orig};
     for (void* p : ps)
         if (p) (void)hipFree(p);
 }

@@ -42,9 +42,17 @@ __device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
 
 // ------------------------------------------------------------------ helpers
 
+// The covariance at scaled distance t = |a - b| / range:
+//   smooth 0: alpha e^{-t}                    (exponential, Matern 1/2)
+//   smooth 1: alpha (1 + t) e^{-t}            (Matern 3/2)
+//   smooth 2: alpha (1 + t + t^2 / 3) e^{-t}  (Matern 5/2)
+//   smooth 3: alpha e^{-t^2}                  (Gaussian)
 __device__ __forceinline__ double cov_t(double t, double alpha, int smooth) {
+    if (smooth == 3) return alpha * exp(-t * t);
     const double e = exp(-t);
-    return smooth ? alpha * (1.0 + t) * e : alpha * e;
+    if (smooth == 0) return alpha * e;
+    if (smooth == 1) return alpha * (1.0 + t) * e;
+    return alpha * ((1.0 + t) + (t * t) / 3.0) * e;
 }
 
 __device__ __forceinline__ double cov_pts(double ax, double ay, double bx, double by, double alpha,

@@ -9,6 +9,8 @@ namespace mra {
 
 enum FoldForm : int8_t { FOLD_FACTOR = 0, FOLD_GRAM = 1 };
 
+constexpr int MAXL_TREE = 16;  // most levels a partition may have
+
 // Host-side description of the partition (Sec. 1.2) plus the execution plan
 // derived from it.  Regions are numbered in level order; the children of
 // region k at level m are J*k .. J*k+J-1 at level m+1, so every region's
@@ -25,6 +27,13 @@ struct HostTree {
     std::vector<double> x, y, z;     // used observations, grouped by leaf
     std::vector<int64_t> orig;       // input index of each used observation
 };
+
+// Builds the partition on the GPU from device-resident x, y, z (no duplicate
+// elimination); the grouped observations and their input indices are
+// returned in new device arrays, t.x / t.y / t.z / t.orig stay empty.
+int build_device_tree(const double* x, const double* y, const double* z, int64_t n, int J, int r, int M,
+                      double offset, const double* domain4, HostTree& t, double** ox, double** oy, double** oz,
+                      int64_t** oorig, std::string& err);
 
 // Builds the partition on the host.  Returns an MRA_* status, message in err.
 int build_host_tree(const double* x, const double* y, const double* z, int64_t n, int J, int r,

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmra.so")
 
 MRA_OK, MRA_EINVAL, MRA_ENOTPD, MRA_ENOMEM, MRA_EDEVICE, MRA_EDOMAIN = 0, -1, -2, -3, -4, -5
-MRA_EXP, MRA_MATERN = 0, 1
+MRA_EXP, MRA_MATERN, MRA_GAUSS = 0, 1, 2
 MRA_DEVICE_PTRS = 1 << 0
 MRA_ELIM_DUPLICATES = 1 << 1
 MRA_ALLOW_ZERO_NUGGET = 1 << 2
@@ -172,7 +172,7 @@ def mfma_peak_tflops(iters: int = 4096) -> float:
 
 
 def family_code(family: str):
-    return {"exp": MRA_EXP, "matern": MRA_MATERN}[family]
+    return {"exp": MRA_EXP, "matern": MRA_MATERN, "gauss": MRA_GAUSS}[family]
 
 
 class Tree:

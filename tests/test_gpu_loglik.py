@@ -131,7 +131,7 @@ def test_invalid_theta_and_family(mra):
         t.loglik([1.0, -0.1, 0.1])
     assert e.value.code == mra.MRA_EINVAL
     with pytest.raises(mra.MraError):
-        t.loglik([1.0, 0.1, 0.1], "matern", 2.5)
+        t.loglik([1.0, 0.1, 0.1], "matern", 3.5)
 
 
 def test_not_positive_definite_is_reported(mra):

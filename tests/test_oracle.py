@@ -283,3 +283,28 @@ def test_errors():
     t = Tree(np.array([0.1, 0.5]), np.array([0.1, 0.5]), np.ones(2), J=4, r=4, M=2)
     with pytest.raises(OracleError):
         t.loglik((1.0, -0.1, 0.1))
+
+
+# ------------------------------------------------ further covariance families
+
+@pytest.mark.parametrize("family,nu", [(MATERN, 2.5), (2, 0.0)])
+def test_more_families_M1_exact_and_recursion_vs_dense(family, nu):
+    """Matern 5/2, (1 + t + t^2/3) e^{-t}, and Gaussian, e^{-t^2}, with t the
+    unscaled distance over the range: M = 1 is the exact Gaussian log-density
+    (SciPy), and the recursion equals the definitional dense path."""
+    rng = np.random.default_rng(17)
+    n = 200
+    x, y, z = rng.random(n), rng.random(n), rng.standard_normal(n)
+    th = (1.2, 0.05, 0.05)
+    t = Tree(x, y, z, J=4, r=16, M=1)
+    a = t.arrays()
+    d = _dist(a["x"], a["y"], a["x"], a["y"]) / th[1]
+    C = th[0] * ((1 + d + d * d / 3.0) * np.exp(-d) if family == MATERN else np.exp(-d * d))
+    ref = multivariate_normal(mean=np.zeros(n), cov=C + th[2] * np.eye(n)).logpdf(a["z"])
+    assert abs(t.loglik(th, family, nu)[0] - ref) <= 1e-11 * abs(ref)
+    c = synth.small_case(211, 600, J=4, r=9, M=3, cluster=True)
+    t3 = Tree(c["x"], c["y"], c["z"], J=4, r=9, M=3)
+    for th3 in [(1.0, 0.03, 0.05), (2.0, 0.06, 0.01)]:
+        a3 = t3.loglik(th3, family, nu)[0]
+        b3 = t3.dense_loglik(th3, family, nu)
+        assert abs(a3 - b3) <= 1e-10 * abs(b3), (th3, a3, b3)
