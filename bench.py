@@ -314,7 +314,8 @@ def main():
             "r_hat": int(info["r_hat"]), "n_theta": int(B), "family": "matern", "nu": 1.5,
             "leaf_obs_min": int(info["leaf_min"]), "leaf_obs_max": int(info["leaf_max"]),
             "whole_path_tflops": all_flops / (ms_step * 1e-3) / 1e12,
-            "plan": None if tune is None else {"fold_max": tune["fold_max"], "small_max": tune["small_max"]},
+            "plan": None if tune is None else {"fold_max": tune["fold_max"], "small_max": tune["small_max"],
+                                               "tile": tune["tile"]},
         },
         "roofline": roof,
     }

@@ -226,7 +226,8 @@ int mra_tree_arrays(const mra_tree *tree, double *x, double *y, double *z, int64
  *
  * mra_autotune times one evaluation of a host sample theta (B x 3) under
  * candidate plans -- per level, the observation-space threshold in
- * {0, 64, ..., 768}, then small_max in {64, 32, 16} -- keeps each choice that
+ * {0, 64, ..., 768}, then per level the tile shape of the knot-space Schur
+ * blocks, then small_max in {64, 32, 16} -- keeps each choice that
  * is at least 2 % faster, installs the best plan in the tree and reports it.
  * mra_set_plan installs a plan directly (fold_max: M - 1 entries for levels
  * 1 .. M-1, -1 = the default rule; or NULL), e.g. one cached from an earlier
@@ -241,10 +242,23 @@ typedef struct mra_tune_result {
     double ms_before;      /* one evaluation of the sample with the plan on entry */
     double ms_after;       /* ... with the plan installed */
     int32_t trials;        /* plans timed */
+    int32_t tile[16];      /* [m - 1]: tile shape of level m's knot-space Schur blocks:
+                              0 64 x 64 blocks (one wave each), 1 128 x 128 super-blocks
+                              (one workgroup each, rows staged through LDS) */
 } mra_tune_result;
 
 int mra_autotune(mra_tree *tree, int family, double nu, const double *theta, int64_t B, mra_tune_result *out);
 int mra_set_plan(mra_tree *tree, const int64_t *fold_max, int small_max);
+
+/*
+ * Tile shape of each level's knot-space Schur blocks (tile: M - 1 entries
+ * for levels 1 .. M-1: -1 the default rule -- super-blocks when the level's
+ * median region has at least 128 rows of observation-space children -- 0
+ * 64 x 64 blocks, 1 128 x 128 super-blocks; NULL: all default).  mra_autotune
+ * also times the alternative shape of every level with knot-space folds.
+ * Same workspace rules as mra_set_plan.
+ */
+int mra_set_tile_shapes(mra_tree *tree, const int32_t *tile);
 
 /*
  * Optional per-launch timing, for measurement.  While enabled, every kernel

@@ -151,6 +151,7 @@ struct Plan {
 struct PlanOpts {
     std::vector<int64_t> fold_max;  // index m = 1 .. M-1
     int small_max = 64;
+    std::vector<int8_t> tile;       // index m: -1 default rule, 0 64 x 64 blocks, 1 128 x 128 super-blocks
 };
 
 struct mra_tree {
@@ -324,6 +325,9 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
     }
     t.root_gram = (M > 1 && t.form[0] == FOLD_GRAM && t.gram_off[0] >= 0) ? 1 : 0;
     plan_flops(h, t);
+    if (opts)
+        for (int m = 1; m < M && m < int(opts->tile.size()); ++m)
+            if (opts->tile[m] >= 0) t.gtile_super[m] = opts->tile[m];
     int rc;
     if ((rc = upload(&t.d_vst_off, t.vst_off)) || (rc = upload(&t.d_gram_off, t.gram_off)) ||
         (rc = upload(&t.d_form, t.form)) || (rc = upload(&t.d_leaf, t.leaf_tasks)) ||
@@ -535,6 +539,7 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
     }
     if (t->leaf_min == INT64_MAX) t->leaf_min = 0;
     t->opts.fold_max.assign(M, -1);
+    t->opts.tile.assign(M, -1);
     if ((rc = make_plan(h, flags, false, nullptr, &t->opts, t->lik, err))) {
         delete t;
         return fail(rc, err);
@@ -1080,6 +1085,17 @@ static int replan(mra_tree* t) {
     return rc ? fail(rc, err) : MRA_OK;
 }
 
+extern "C" int mra_set_tile_shapes(mra_tree* t, const int32_t* tile) {
+    if (!t) return fail(MRA_EINVAL, "NULL tree");
+    const int M = t->h.M;
+    for (int m = 1; m < M; ++m) {
+        const int32_t v = tile ? tile[m - 1] : -1;
+        if (v < -1 || v > 1) return fail(MRA_EINVAL, "tile shapes must be -1, 0 or 1");
+        t->opts.tile[m] = int8_t(v);
+    }
+    return replan(t);
+}
+
 extern "C" int mra_set_plan(mra_tree* t, const int64_t* fold_max, int small_max) {
     if (!t) return fail(MRA_EINVAL, "NULL tree");
     if (small_max != 16 && small_max != 32 && small_max != 64) return fail(MRA_EINVAL, "small_max must be 16, 32 or 64");
@@ -1161,6 +1177,19 @@ extern "C" int mra_autotune(mra_tree* t, int family, double nu, const double* th
         t->opts.fold_max[m] = best_v;
         if ((rc = replan(t))) return rc;
     }
+    // the Schur blocks' tile shape per level with knot-space folds
+    for (int m = M - 1; m >= 2; --m) {
+        if (t->lik.gram_tasks[m].empty()) continue;
+        const int8_t cur = t->lik.gtile_super[m];
+        const int8_t keep = t->opts.tile[m];
+        t->opts.tile[m] = cur ? 0 : 1;
+        if ((rc = replan(t))) return rc;
+        double ms = 0.0;
+        if ((rc = time_plan(&ms))) return rc;
+        if (ms < 0.98 * ms_best) ms_best = ms;
+        else t->opts.tile[m] = keep;
+    }
+    if ((rc = replan(t))) return rc;
     for (int sm : {32, 16}) {
         const int keep = t->opts.small_max;
         t->opts.small_max = sm;
@@ -1178,6 +1207,7 @@ extern "C" int mra_autotune(mra_tree* t, int family, double nu, const double* th
         out->fold_max[m - 1] = v >= 0 ? v : std::min<int64_t>(int64_t(m - 1) * h.P + 1, factor_fold_max());
     }
     out->small_max = t->opts.small_max;
+    for (int m = 1; m < M && m <= 16; ++m) out->tile[m - 1] = t->lik.gtile_super[m];
     out->ms_before = ms_before;
     out->ms_after = ms_best;
     out->trials = trials;

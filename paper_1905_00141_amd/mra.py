@@ -27,7 +27,7 @@ EXPORTED = ["mra_build_tree", "mra_loglik", "mra_loglik_terms", "mra_loglik_leve
             "mra_loglik_noalloc",
             "mra_predict", "mra_free_tree", "mra_last_error",
             "mra_tree_info", "mra_tree_arrays", "mra_profile_enable", "mra_profile_read",
-            "mra_autotune", "mra_set_plan", "mra_bench_mfma_f64",
+            "mra_autotune", "mra_set_plan", "mra_set_tile_shapes", "mra_bench_mfma_f64",
             "mra_mlp_create", "mra_mlp_set_scaling", "mra_mlp_forward", "mra_mlp_loss_grad",
             "mra_mlp_train_step", "mra_mlp_get_params", "mra_mlp_free"]
 MLP_WIDTH = 128
@@ -44,7 +44,8 @@ class MraInfo(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("levels", C.c_int32), ("small_max", C.c_int32), ("fold_max", C.c_int64 * 16),
-                ("ms_before", C.c_double), ("ms_after", C.c_double), ("trials", C.c_int32)]
+                ("ms_before", C.c_double), ("ms_after", C.c_double), ("trials", C.c_int32),
+                ("tile", C.c_int32 * 16)]
 
 
 class KernelStat(C.Structure):
@@ -94,6 +95,8 @@ def load_library(path: str = LIB_PATH):
     L.mra_autotune.restype = C.c_int
     L.mra_set_plan.argtypes = [vp, vp, C.c_int]
     L.mra_set_plan.restype = C.c_int
+    L.mra_set_tile_shapes.argtypes = [vp, vp]
+    L.mra_set_tile_shapes.restype = C.c_int
     L.mra_bench_mfma_f64.argtypes = [i64, C.POINTER(C.c_double)]
     L.mra_bench_mfma_f64.restype = C.c_int
     f32 = C.c_float
@@ -257,7 +260,17 @@ class Tree:
         r = TuneResult()
         _check(_lib.mra_autotune(self._h, family_code(family), float(nu), th.ctypes.data, th.shape[0], C.byref(r)))
         return dict(fold_max=[int(r.fold_max[i]) for i in range(r.levels - 1)], small_max=int(r.small_max),
+                    tile=[int(r.tile[i]) for i in range(r.levels - 1)],
                     ms_before=r.ms_before, ms_after=r.ms_after, trials=int(r.trials))
+
+    def set_tile_shapes(self, tile=None):
+        """Schur-block tile shape per level 1 .. M-1 (-1 default, 0 64 x 64, 1 128 x 128)."""
+        if tile is None:
+            _check(_lib.mra_set_tile_shapes(self._h, None))
+            return
+        tl = np.ascontiguousarray(tile, dtype=np.int32)
+        assert tl.shape == (self.info["M"] - 1,)
+        _check(_lib.mra_set_tile_shapes(self._h, tl.ctypes.data))
 
     def set_plan(self, fold_max=None, small_max=64):
         """Install an execution plan (per-level fold thresholds, -1 = default rule)."""

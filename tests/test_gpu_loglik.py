@@ -253,6 +253,16 @@ def test_autotune_and_set_plan_keep_parity(mra, oracle):
         assert np.all(_rel(got, ref) <= RTOL), (fm, sm, _rel(got, ref))
     with pytest.raises(mra.MraError):
         t.set_plan(None, 48)
+    # every Schur-block tile shape keeps the result
+    for tl in ([0, 0, 0, 0], [1, 1, 1, 1], [-1, 0, 1, 0]):
+        t.set_plan([0, 0, 0, 0], 64)
+        t.set_tile_shapes(tl)
+        got = t.loglik(THETAS, "matern", 1.5)
+        assert np.all(_rel(got, ref) <= RTOL), (tl, _rel(got, ref))
+    t.set_tile_shapes(None)
+    with pytest.raises(mra.MraError):
+        t.set_tile_shapes([2, 0, 0, 0])
+    assert len(res["tile"]) == 4
     tg = mra.Tree(c["x"], c["y"], c["z"], J=4, r=30, M=5, flags=mra.MRA_FOLD_GRAM)
     with pytest.raises(mra.MraError):
         tg.autotune(THETAS[:1])
