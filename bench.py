@@ -228,21 +228,22 @@ def main():
     out = torch.empty(B, dtype=torch.float64, device=dev)
     stream = torch.cuda.Stream(device=dev)
 
-    # warmup; the first warmup step is profiled per launch to find the dominant kernel
-    breakdown = None
+    # warmup (the first device-pointer call also captures the launch graph),
+    # then one step profiled per launch, in steady state, for the breakdown
     for i in range(max(args.warmup, 1)):
         t1 = time.time()
-        if i == 0:
-            mra.profile_enable(True)
         tree.loglik(theta, cfg["family"], cfg["nu"], out=out, stream=stream)
         stream.synchronize()
-        if i == 0:
-            mra.profile_enable(False)
-            breakdown = mra.profile_read()
         log(f"[bench] warmup step {i} {time.time() - t1:.3f} s")
     ll = out.cpu().numpy()
     assert np.all(np.isfinite(ll)), ll
+    mra.profile_enable(True)
+    tree.loglik(theta, cfg["family"], cfg["nu"], out=out, stream=stream)
+    stream.synchronize()
+    mra.profile_enable(False)
+    breakdown = mra.profile_read()
     tot_ms = sum(s["ms"] for s in breakdown)
+    log(f"[bench] profiled step: {tot_ms:.1f} ms of kernel time")
     for s in sorted(breakdown, key=lambda s: -s["ms"]):
         tf = s["flops"] / (s["ms"] * 1e-3) / 1e12 if s["ms"] > 0 else 0.0
         log(f"[bench] {s['name']:14s} L{s['level']:<2d} launches {s['launches']:4d} "

@@ -309,20 +309,43 @@ __device__ __forceinline__ bool wg_potrf_inv_lds(double* T, int n, int ld, doubl
     return bad;
 }
 
+// 1/sqrt(x) and sqrt(x) for x > 0: the hardware reciprocal-square-root
+// estimate refined by two Newton steps (y <- y + y (1 - x y^2) / 2), then one
+// Newton step for the square root (s <- s + (x - s^2) y / 2).
+__device__ __forceinline__ void rsqrt_sqrt(double x, double& rs, double& sd) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    double s = x * y;
+    s = fma(0.5 * y, fma(-s, s, x), s);
+    rs = y;
+    sd = s;
+}
+
 // Cholesky factor and its inverse of an n x n (n <= 16 NB) lower triangle held
-// in a 16 NB x 16 NB LDS tile T (pitch ld), by one wave, with no workgroup barrier:
-// on return T holds L^{-1} (lower, zeros above the diagonal, identity beyond
-// n) where L L^T is the input, and *logdet = sum log diag L.  Returns true
-// (uniformly) when a pivot is not positive.
-// The tile is processed in 16 x 16 blocks, right-looking: each diagonal block
-// is factored in registers (lane r of every 16-lane group holds row r; the
-// column of the factor is broadcast with lane reads) and inverted by forward
-// substitution with broadcast LDS reads; the panel below it is multiplied by
-// that inverse and the trailing blocks are updated on the matrix cores.  The
-// off-diagonal blocks of L^{-1} then follow block row by block row:
-// X_ij = -D_i^{-1} sum_{k=j}^{i-1} L_ik X_kj with D_i^{-1} the diagonal
-// inverses.
-template <int NB>
+// in a 16 NB x 16 NB LDS tile T (pitch ld > 16 NB), by one wave, with no
+// workgroup barrier: on return T holds L^{-1} (lower, zeros above the
+// diagonal, identity beyond n) where L L^T is the input, and *logdet = sum
+// log diag L.  Returns true (uniformly) when a pivot is not positive.  Entries
+// of T above the diagonal are neither read as data nor preserved; column
+// 16 NB (the padding) is scratch.
+// The tile is processed in 16 x 16 blocks, right-looking.  A diagonal block is
+// factored in registers, lane r of every 16-lane group holding row r, each
+// column of the factor broadcast by lane reads.  Entries right of the
+// diagonal in a lane's row are carried along but never used (no per-lane
+// conditions: they would be kept as lane masks).  The block is inverted by forward
+// substitution, lane c solving for column c, with the reciprocal square roots
+// of the pivots as the diagonal of the inverse.  The panel below is
+// multiplied by that inverse and the trailing blocks are updated on the
+// matrix cores.  The off-diagonal blocks of L^{-1} then follow block row by
+// block row: X_ij = -D_i^{-1} sum_{k=j}^{i-1} L_ik X_kj with D_i^{-1} the
+// diagonal inverses.  The pivots' product is kept as a mantissa and a binary
+// exponent, so that one logarithm serves the whole tile.  PD bounds how many
+// rows ahead the inverse's LDS reads may be issued (0: no bound; a caller
+// whose registers allow it and whose LDS latency is high under load wants 0).
+template <int NB, int PD = 2>
 __device__ __forceinline__ bool wave_chol_inv(double* T, int ld, int n, double* logdet) {
     constexpr int NT16 = 16 * NB;
     const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
@@ -333,52 +356,62 @@ __device__ __forceinline__ bool wave_chol_inv(double* T, int ld, int n, double* 
     }
     wsync();
     bool bad = false;
-    double lsum = 0.0;
+    double pp = 1.0;  // product of the pivots: mantissa pp, binary exponent pe
+    int pe = 0;
 #pragma unroll
     for (int kb = 0; kb < NB; ++kb) {
         double* Dg = T + 16 * kb * ld + 16 * kb;
-        // (1) factor the 16 x 16 diagonal block; lane r (r = lr) keeps row r
+        // (1) factor the 16 x 16 diagonal block
         double d[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) d[k] = (k <= lr) ? Dg[lr * ld + k] : 0.0;
-        double pp = 1.0;  // product of four pivots: one logarithm per four columns
+        for (int k = 0; k < 16; ++k) d[k] = Dg[lr * ld + k];
+        wsync();
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const double piv = bcast(d[j], j);
             bad = bad || !(piv > 0.0);
             const double pv = piv > 0.0 ? piv : 1.0;
-            const double sd = sqrt(pv);
             pp *= pv;
             if ((j & 3) == 3) {
-                lsum += 0.5 * log(pp);
-                pp = 1.0;
+                pe += __builtin_amdgcn_frexp_exp(pp);
+                pp = __builtin_amdgcn_frexp_mant(pp);
             }
-            const double rs = 1.0 / sd;
-            const double lij = (lr > j) ? d[j] * rs : (lr == j ? sd : 0.0);
+            double rs, sd;
+            rsqrt_sqrt(pv, rs, sd);
+            (void)sd;
+            T[(16 * kb + j) * ld + 16 * NB] = rs;  // for the inverse
+            // column j of the factor; on lane j the pivot times its reciprocal
+            // square root, i.e. the diagonal entry
+            const double lij = d[j] * rs;
             d[j] = lij;
 #pragma unroll
             for (int k = j + 1; k < 16; ++k) d[k] = fma(-lij, bcast(lij, k), d[k]);
         }
         wsync();
-        if (lg == 0) {
 #pragma unroll
-            for (int k = 0; k < 16; ++k)
-                if (k <= lr) Dg[lr * ld + k] = d[k];
-        }
+        for (int k = 0; k < 16; ++k) Dg[lr * ld + k] = d[k];
         wsync();
-        // (2) its inverse: lane c computes column c by forward substitution
+        // (2) its inverse: entries above the diagonal come out zero, since
+        // their right-hand side and every earlier entry of the column are
         double x[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             double acc = (q == lr) ? 1.0 : 0.0;
+            // with PD > 0, row q is read once x[q - PD] exists: its offset
+            // depends on x[q - PD] (one element further on for a NaN, which
+            // only a failed factor produces; still inside row q), so that the
+            // compiler does not load every row up front where registers are
+            // short (they would spill)
+            int off = q * ld;
+            if (PD > 0 && q >= PD) off += (x[q - PD] != x[q - PD]) ? 1 : 0;
 #pragma unroll
-            for (int k = 0; k < q; ++k) acc = fma(-Dg[q * ld + k], x[k], acc);
-            x[q] = (q >= lr) ? acc / Dg[q * ld + q] : 0.0;
+            for (int k = 0; k < q; ++k) acc = fma(-Dg[off + k], x[k], acc);
+            x[q] = acc * T[(16 * kb + q) * ld + 16 * NB];
         }
         wsync();
         if (lg == 0) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) Dg[q * ld + lr] = x[q];  // zeros above the diagonal
+            for (int q = 0; q < 16; ++q) Dg[q * ld + lr] = x[q];
         }
         wsync();
         // (3) panel: L_ib = A_ib D^{-T} for the blocks below
@@ -409,37 +442,53 @@ __device__ __forceinline__ bool wave_chol_inv(double* T, int ld, int n, double* 
             }
         wsync();
     }
-    // (5) off-diagonal blocks of L^{-1}, block row by block row
+    // (5) off-diagonal blocks of L^{-1}, block row by block row; the operands
+    // of a block are loaded before its products
 #pragma unroll
     for (int ib = 1; ib < NB; ++ib) {
-        v4d out[NB > 1 ? NB - 1 : 1];
+        v4d z[NB > 1 ? NB - 1 : 1];
 #pragma unroll
         for (int jb = 0; jb < ib; ++jb) {
-            v4d y = v4d{0.0, 0.0, 0.0, 0.0};
+            double av[NB][4], bv[NB][4], dv[4];
 #pragma unroll
             for (int k = jb; k < ib; ++k)
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    y = mfma(T[(16 * ib + lr) * ld + 16 * k + 4 * q + lg], T[(16 * k + 4 * q + lg) * ld + 16 * jb + lr], y);
-            v4d z = v4d{0.0, 0.0, 0.0, 0.0};
+                for (int q = 0; q < 4; ++q) {
+                    av[k][q] = T[(16 * ib + lr) * ld + 16 * k + 4 * q + lg];
+                    bv[k][q] = T[(16 * k + 4 * q + lg) * ld + 16 * jb + lr];
+                }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) z = mfma(-T[(16 * ib + lr) * ld + 16 * ib + 4 * e + lg], y[e], z);
-            out[jb] = z;
+            for (int e = 0; e < 4; ++e) dv[e] = -T[(16 * ib + lr) * ld + 16 * ib + 4 * e + lg];
+            v4d y0 = v4d{0.0, 0.0, 0.0, 0.0}, y1 = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = jb; k < ib; ++k)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q & 1) y1 = mfma(av[k][q], bv[k][q], y1);
+                    else y0 = mfma(av[k][q], bv[k][q], y0);
+                }
+            const v4d y = y0 + y1;
+            v4d zz = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) zz = mfma(dv[e], y[e], zz);
+            z[jb] = zz;
         }
         wsync();
 #pragma unroll
         for (int jb = 0; jb < ib; ++jb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) T[(16 * ib + lg + 4 * i) * ld + 16 * jb + lr] = out[jb][i];
+            for (int i = 0; i < 4; ++i) T[(16 * ib + lg + 4 * i) * ld + 16 * jb + lr] = z[jb][i];
         wsync();
     }
-    // zeros above the diagonal blocks
-    for (int e = lane; e < NT16 * NT16; e += 64) {
-        const int i = e / NT16, j = e % NT16;
-        if ((j >> 4) > (i >> 4)) T[i * ld + j] = 0.0;
-    }
+    // zeros in the blocks above the diagonal
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int jb = ib + 1; jb < NB; ++jb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) T[(16 * ib + lg + 4 * i) * ld + 16 * jb + lr] = 0.0;
     wsync();
-    *logdet = lsum;
+    *logdet = 0.5 * (log(pp) + double(pe) * 0.69314718055994530942);
     return bad;
 }
 

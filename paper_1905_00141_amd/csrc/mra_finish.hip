@@ -6,8 +6,8 @@ namespace mra {
 
 // Level-m regions, one wave per region: W = C(Q_R, Q_R) - sum_{i<m} V^i V^i^T
 // (lower 16x16 tiles on the matrix cores, padded with an identity block), its
-// Cholesky factor and inverse; the inverse is stored as the last block of the
-// region's V store.
+// Cholesky factor and inverse (the one-wave blocked factorization); the
+// inverse is stored as the last block of the region's V store.
 template <int P>
 __global__ void __launch_bounds__(NT) k_prior_finish_w(KArgs a) {
     constexpr int NM = P / 16, NT2 = NM * (NM + 1) / 2;
@@ -78,8 +78,12 @@ __global__ void __launch_bounds__(NT) k_prior_finish_w(KArgs a) {
                 }
         }
         wsync();
-        // factor in LDS; the inverse goes straight to its place in the V store
-        if (wave_potrf_inv<P>(Tw, LDT, V + (m - 1) * P, ld, P) && lane == 0) atomicCAS(a.status + th, 0, int(g + 1));
+        // factor and inverse in LDS, then the inverse to its place in the V store
+        double ldv;
+        if (wave_chol_inv<NM>(Tw, LDT, P, &ldv) && lane == 0) atomicCAS(a.status + th, 0, int(g + 1));
+        double* Li = V + (m - 1) * P;
+        for (int e = lane; e < P * P; e += 64) Li[int64_t(e / P) * ld + (e % P)] = Tw[(e / P) * LDT + (e % P)];
+        wsync();  // the wave's next task rewrites its tile
     }
 }
 

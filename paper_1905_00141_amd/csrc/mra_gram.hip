@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(NT, 2) k_gram_panel(KArgs a) {
         // one wave: the factor's inverse replaces the tile
         if ((threadIdx.x >> 6) == 0) {
             double ldv = 0.0;
-            const bool bad = wave_chol_inv64(s.L, MLD, P, &ldv);
+            const bool bad = wave_chol_inv<4, 0>(s.L, MLD, P, &ldv);
             if (threadIdx.x == 0) { s.flag = bad ? 1 : 0; s.Li[0] = ldv; }
         }
         __syncthreads();

@@ -134,10 +134,14 @@ def test_invalid_theta_and_family(mra):
         t.loglik([1.0, 0.1, 0.1], "matern", 3.5)
 
 
-def test_not_positive_definite_is_reported(mra):
-    # two observations at the same location with a vanishing nugget: the
-    # finest-level covariance is singular in FP64
-    x = np.array([0.3, 0.3, 0.8]); y = np.array([0.3, 0.3, 0.8]); z = np.array([1.0, 1.0, 0.5])
+@pytest.mark.parametrize("ndup", [24, 80])
+def test_not_positive_definite_is_reported(mra, ndup):
+    # ndup observations at one location with a vanishing nugget: the
+    # finest-level covariance has rank 1 plus the nugget, which FP64 loses, so
+    # its Cholesky factorization meets ndup - 1 pivots that are rounding noise
+    # (one of them non-positive); 24 rows run on the one-wave finisher, 80 on
+    # the workgroup finisher
+    x = np.r_[np.full(ndup, 0.3), 0.8]; y = np.r_[np.full(ndup, 0.3), 0.8]; z = np.r_[np.ones(ndup), 0.5]
     t = mra.Tree(x, y, z, J=4, r=4, M=2, domain=[0, 1, 0, 1])
     with pytest.raises(mra.MraError) as e:
         t.loglik([1.0, 0.1, 1e-300])

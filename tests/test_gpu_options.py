@@ -80,14 +80,14 @@ def test_leaf_histogram(mra):
 
 def test_status_query_for_device_pointers(mra):
     import torch
-    x = np.array([0.3, 0.3, 0.8, 0.1]); y = np.array([0.3, 0.3, 0.8, 0.6]); z = np.array([1.0, 1.0, 0.5, 0.2])
+    x = np.r_[np.full(24, 0.3), 0.8, 0.1]; y = np.r_[np.full(24, 0.3), 0.8, 0.6]; z = np.r_[np.ones(24), 0.5, 0.2]
     t = mra.Tree(x, y, z, J=4, r=4, M=2, domain=[0, 1, 0, 1])
     dev = torch.device("cuda:0")
     good = torch.tensor([[1.0, 0.1, 0.1]], dtype=torch.float64, device=dev)
     out = t.loglik(good)
     t.status()
     assert np.isfinite(out.cpu().numpy()).all()
-    # a repeated location with a vanishing nugget: singular finest-level matrix
+    # a location repeated 24 times with a vanishing nugget: singular finest-level matrix
     bad = torch.tensor([[1.0, 0.1, 0.1], [1.0, 0.1, 1e-300]], dtype=torch.float64, device=dev)
     out = t.loglik(bad)
     with pytest.raises(mra.MraError) as e:
