@@ -36,6 +36,8 @@ hipError_t launch_pred_fold(const KArgs& a, hipStream_t st);
 hipError_t launch_pred_out(const KArgs& a, hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_fill_int(int* p, int64_t n, int v, hipStream_t st);
+hipError_t launch_rep(const double* theta, int nb, int* rep, hipStream_t st);
+hipError_t launch_rep_status(const int* rep, int nb, int* status, hipStream_t st);
 }  // namespace mra
 
 namespace mra {
@@ -640,11 +642,15 @@ static KArgs base_args(const mra_tree* t, const Plan& pl, int smooth) {
     a.d_stride = h.nreg;
     a.n_used = double(h.n_used);
     a.zero_nugget = (t->flags & MRA_ALLOW_ZERO_NUGGET) ? 1 : 0;
+    a.rep = nullptr;
+    a.leaf_phase = -1;
     return a;
 }
 
 // Prior (levels 1..M-1) and the observations' whitened rows for one chunk.
-static hipError_t enqueue_prior(const mra_tree* t, const Plan& pl, KArgs a, int nb, hipStream_t st) {
+// nth: theta the prior is computed for (the flop count of the profiler).
+static hipError_t enqueue_prior(const mra_tree* t, const Plan& pl, KArgs a, int nb, hipStream_t st, double nth = -1) {
+    if (nth < 0) nth = nb;
     const int M = t->h.M;
     hipError_t e;
     for (int m = 1; m < M; ++m) {
@@ -653,35 +659,38 @@ static hipError_t enqueue_prior(const mra_tree* t, const Plan& pl, KArgs a, int 
         a.ntasks = int64_t(pl.prior_tasks[m].size());
         if (a.ntasks == 0) continue;
         const int grid = int(std::min<int64_t>(a.ntasks * nb, 1 << 16));
-        if (m > 1 && (e = timed(0, m, pl.fl_chain[m] * nb, st, [&] { return launch_chain(a, 0, grid, st); }))) return e;
-        if ((e = timed(1, m, pl.fl_pfin[m] * nb, st, [&] { return launch_prior_finish(a, grid, st); }))) return e;
+        if (m > 1 && (e = timed(0, m, pl.fl_chain[m] * nth, st, [&] { return launch_chain(a, 0, grid, st); }))) return e;
+        if ((e = timed(1, m, pl.fl_pfin[m] * nth, st, [&] { return launch_prior_finish(a, grid, st); }))) return e;
     }
     if (M > 1 && !pl.chain_obs_tasks.empty()) {
         a.level = M - 1;
         a.tasks = pl.d_chain_obs;
         a.ntasks = int64_t(pl.chain_obs_tasks.size());
         const int grid = int(std::min<int64_t>(a.ntasks * nb, 1 << 16));
-        if ((e = timed(0, M, pl.fl_chain_obs * nb, st, [&] { return launch_chain(a, 1, grid, st); }))) return e;
+        if ((e = timed(0, M, pl.fl_chain_obs * nth, st, [&] { return launch_chain(a, 1, grid, st); }))) return e;
     }
     return hipSuccess;
 }
 
 // Finest-level factors of the observations for one chunk.
-static hipError_t enqueue_leaves(const mra_tree* t, const Plan& pl, KArgs a, int nb, int64_t nslot, hipStream_t st) {
+// nth: theta whose tasks run in this launch sequence (the flop count).
+static hipError_t enqueue_leaves(const mra_tree* t, const Plan& pl, KArgs a, int nb, int64_t nslot, hipStream_t st,
+                                 double nth = -1) {
+    if (nth < 0) nth = nb;
     const int M = t->h.M;
     hipError_t e;
     a.level = M;
     for (int q = 0; q < 3; ++q) {
         a.tasks = pl.d_small[q];
         a.ntasks = int64_t(pl.small_tasks[q].size());
-        if (a.ntasks > 0 && (e = timed(6, M, pl.fl_small[q] * nb, st, [&] {
+        if (a.ntasks > 0 && (e = timed(6, M, pl.fl_small[q] * nth, st, [&] {
                                  return launch_small(a, 16 << q, 0, int(std::min<int64_t>(a.ntasks * nb, 1 << 18)), st);
                              })))
             return e;
     }
     a.tasks = pl.d_leaf;
     a.ntasks = int64_t(pl.leaf_tasks.size());
-    if (a.ntasks > 0 && (e = timed(2, M, pl.fl_leaf * nb, st, [&] {
+    if (a.ntasks > 0 && (e = timed(2, M, pl.fl_leaf * nth, st, [&] {
                              return launch_leaf(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st);
                          })))
         return e;
@@ -739,6 +748,7 @@ struct Workspace {
     double *vst = nullptr, *F = nullptr, *gram = nullptr, *dval = nullptr, *scratch = nullptr;
     double *th = nullptr, *out = nullptr, *ld = nullptr, *q = nullptr;
     int* status = nullptr;
+    int* rep = nullptr;  // per theta of a chunk: its representative (shared prior)
     int64_t Bc = 0, nslot = 0, scratch_per = 0, cap_B = 0;
     bool mem_limited = false;  // Bc was capped by device memory, not by the request
     hipEvent_t done = nullptr;
@@ -758,10 +768,10 @@ struct Workspace {
         for (void* p : {static_cast<void*>(vst), static_cast<void*>(F), static_cast<void*>(gram),
                         static_cast<void*>(dval), static_cast<void*>(scratch), static_cast<void*>(th),
                         static_cast<void*>(out), static_cast<void*>(ld), static_cast<void*>(q),
-                        static_cast<void*>(status)})
+                        static_cast<void*>(status), static_cast<void*>(rep)})
             if (p) (void)hipFree(p);
         vst = F = gram = dval = scratch = th = out = ld = q = nullptr;
-        status = nullptr;
+        status = rep = nullptr;
         Bc = nslot = cap_B = 0;
         used = false;
     }
@@ -810,6 +820,7 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
         !al(reinterpret_cast<void**>(&w.dval), size_t(Bc) * h.nreg * 8) ||
         !al(reinterpret_cast<void**>(&w.scratch), size_t(nslot) * scratch_per * 8) ||
         !al(reinterpret_cast<void**>(&w.status), size_t(capB) * sizeof(int)) ||
+        !al(reinterpret_cast<void**>(&w.rep), size_t(capB) * sizeof(int)) ||
         !al(reinterpret_cast<void**>(&w.th), size_t(capB) * 3 * 8) ||
         !al(reinterpret_cast<void**>(&w.out), size_t(capB) * 8) ||
         !al(reinterpret_cast<void**>(&w.ld), size_t(capB) * 8) ||
@@ -833,13 +844,23 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
 
 // Every launch of one evaluation of B parameter vectors, in chunks of Bc
 // theta (the per-theta buffers of a.vst, a.F, a.gram, a.dval hold Bc theta;
-// nslot workgroup slots of a.scratch).
+// nslot workgroup slots of a.scratch).  With rep_buf (Bc ints on the device),
+// theta of a chunk that share alpha and range share the prior: it is computed
+// for the first of them (the representative), the others' finest-level
+// finishers read its rows before the representative's own finisher
+// overwrites them.  Which theta share is found on the device, so that a
+// captured graph stays valid for new values in the same buffer.
 static hipError_t enqueue_loglik(const mra_tree* t, int64_t Bc, int64_t nslot, KArgs a, const double* d_th,
                                  double* d_out, double* d_ld, double* d_q, int* status, int64_t B, hipStream_t st,
-                                 double* d_lev = nullptr) {
+                                 double* d_lev = nullptr, int* rep_buf = nullptr) {
     const HostTree& h = t->h;
     const Plan& pl = t->lik;
     hipError_t e;
+    bool prof;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        prof = g_prof_on;
+    }
     if ((e = launch_fill_int(status, B, 0, st))) return e;
     for (int64_t b0 = 0; b0 < B; b0 += Bc) {
         const int nb = int(std::min<int64_t>(Bc, B - b0));
@@ -850,14 +871,51 @@ static hipError_t enqueue_loglik(const mra_tree* t, int64_t Bc, int64_t nslot, K
         a.out_ld = d_ld ? d_ld + b0 : nullptr;
         a.out_q = d_q ? d_q + b0 : nullptr;
         a.out_lev = d_lev ? d_lev + b0 * h.M : nullptr;
+        const bool share = rep_buf && nb > 1 && h.M > 1;
+        double nrep = nb;  // representatives (the profiler's flop count; eager launches only)
+        if (share && prof) {
+            std::vector<double> th(size_t(3) * nb);
+            if ((e = hipMemcpyAsync(th.data(), a.theta, th.size() * 8, hipMemcpyDeviceToHost, st))) return e;
+            if ((e = hipStreamSynchronize(st))) return e;
+            nrep = 0;
+            for (int i = 0; i < nb; ++i) {
+                bool first = true;
+                for (int j = 0; j < i && first; ++j)
+                    first = !(th[3 * j] == th[3 * i] && th[3 * j + 1] == th[3 * i + 1]);
+                nrep += first ? 1 : 0;
+            }
+        }
+        a.rep = nullptr;
+        a.leaf_phase = -1;
+        if (share) {
+            if ((e = launch_rep(a.theta, nb, rep_buf, st))) return e;
+            a.rep = rep_buf;
+        }
         if ((e = launch_fill(a.dval, int64_t(nb) * a.d_stride, 0.0, st))) return e;
-        if ((e = enqueue_prior(t, pl, a, nb, st))) return e;
-        if ((e = enqueue_leaves(t, pl, a, nb, nslot, st))) return e;
+        if ((e = enqueue_prior(t, pl, a, nb, st, nrep))) return e;
+        if (share) {
+            if ((e = launch_rep_status(a.rep, nb, a.status, st))) return e;
+            a.leaf_phase = 0;  // the theta that share a prior, from their representative's rows
+            if ((e = enqueue_leaves(t, pl, a, nb, nslot, st, nb - nrep))) return e;
+            a.leaf_phase = 1;  // then the representatives, in place
+            if ((e = enqueue_leaves(t, pl, a, nb, nslot, st, nrep))) return e;
+            a.rep = nullptr;
+            a.leaf_phase = -1;
+        } else if ((e = enqueue_leaves(t, pl, a, nb, nslot, st))) {
+            return e;
+        }
         for (int m = h.M - 1; m >= 1; --m)
             if ((e = enqueue_fold(t, pl, a, m, nb, nslot, st))) return e;
         if ((e = timed(5, 0, 0.0, st, [&] { return launch_final(a, h.nreg, pl.root_gram, st); }))) return e;
     }
     return hipSuccess;
+}
+
+// Sharing of the prior between theta with the same alpha and range is on
+// unless MRA_SHARE_PRIOR=0.
+static bool share_enabled() {
+    const char* e = std::getenv("MRA_SHARE_PRIOR");
+    return !(e && *e == '0');
 }
 
 // Repeated evaluations with device pointers on a non-null stream replay a
@@ -911,18 +969,21 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
         std::lock_guard<std::mutex> pk(g_prof_mu);
         profiling = g_prof_on;
     }
+    const bool share = share_enabled();
+    int* rep_buf = share ? w.rep : nullptr;
     if (!dev) HIPCHK(hipMemcpyAsync(d_th, theta, 3 * B * 8, hipMemcpyHostToDevice, st));
     if (dev && st != nullptr && !profiling && graphs_enabled() && !levels) {
         // a repeated evaluation on the same buffers replays one captured graph
         const auto key = std::make_tuple(static_cast<const void*>(theta), static_cast<void*>(loglik),
-                                         static_cast<void*>(logdet), static_cast<void*>(quad), B, smooth,
-                                         static_cast<void*>(st));
+                                         static_cast<void*>(logdet), static_cast<void*>(quad), B,
+                                         smooth + (share ? 16 : 0), static_cast<void*>(st));
         auto it = w.graphs.find(key);
         if (it == w.graphs.end()) {
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
             HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            const hipError_t ce = enqueue_loglik(t, w.Bc, w.nslot, a, d_th, d_out, d_ld, d_q, w.status, B, st);
+            const hipError_t ce =
+                enqueue_loglik(t, w.Bc, w.nslot, a, d_th, d_out, d_ld, d_q, w.status, B, st, nullptr, rep_buf);
             const hipError_t ee = hipStreamEndCapture(st, &g);
             HIPCHK(ce);
             HIPCHK(ee);
@@ -933,7 +994,7 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
         }
         HIPCHK(hipGraphLaunch(it->second, st));
     } else {
-        HIPCHK(enqueue_loglik(t, w.Bc, w.nslot, a, d_th, d_out, d_ld, d_q, w.status, B, st, d_lev));
+        HIPCHK(enqueue_loglik(t, w.Bc, w.nslot, a, d_th, d_out, d_ld, d_q, w.status, B, st, d_lev, rep_buf));
     }
     (void)hipEventRecord(w.done, st);
     w.last = st;

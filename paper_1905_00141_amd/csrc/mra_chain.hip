@@ -7,7 +7,8 @@ namespace mra {
 // (a.level = m) for ancestors 1..m-1, written into the region's V store
 // (row-major P x mP, block i-1 = V^i).  mode 1: every observation under a
 // level-(M-1) region for ancestors 1..M-1, written into the F buffer (block of
-// level l at columns (M-1-l)P).  For ancestor level l, with C the covariance:
+// level l at columns (M-1-l)P, the observation's value in the last column).
+// For ancestor level l, with C the covariance:
 //     V^l = ( C(rows, Q_{A_l}) - sum_{i<l} V^i V^i(Q_{A_l})^T ) L_{A_l}^{-T}.
 // Each wave owns 16 rows.  Ancestor levels are taken in groups of GS = 128/P:
 // one pending accumulator per level of the group (MFMA destinations, knots x
@@ -78,6 +79,7 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
     for (int q = threadIdx.x; q < P; q += NT) kq[q] = q < a.rhat ? (q % a.nx) + 8 * (q / a.nx) : -1;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         const int th = int(t / a.ntasks);
+        if (a.rep && a.rep[th] != th) continue;  // shares its representative's prior
         const int64_t g = a.tasks[t % a.ntasks];
         const int64_t k = g - a.lvl[m - 1];
         const double* thp = a.theta + 3 * th;
@@ -153,6 +155,7 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
                 else knot_xy(a, g, rr, px, py);
             }
             double* drow = dst + int64_t(rr) * ldd;
+            if (mode == 1 && store) drow[a.WF - 1] = a.z[lo + rr];  // the data column of [V | z]
             auto colof = [&](int i) -> int64_t { return mode == 0 ? int64_t(i) * P : int64_t(a.M - 2 - i) * P; };
             for (int g0 = 0; g0 < L; g0 += GS) {
                 v4d acc[GS][NM];

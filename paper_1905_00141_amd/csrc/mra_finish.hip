@@ -19,6 +19,7 @@ __global__ void __launch_bounds__(NT) k_prior_finish_w(KArgs a) {
     double* Tw = T[w];
     for (int64_t t = int64_t(blockIdx.x) * 4 + w; t < total; t += int64_t(gridDim.x) * 4) {
         const int th = int(t / a.ntasks);
+        if (a.rep && a.rep[th] != th) continue;  // shares its representative's prior
         const int64_t g = a.tasks[t % a.ntasks];
         const double* thp = a.theta + 3 * th;
         const double alpha = thp[0], inv_beta = 1.0 / thp[1];
@@ -114,12 +115,15 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 3 : 1)) k_small(KArgs a) {
     const int tc0 = MODE == FIN_LEAF ? 0 : kc0 + P;                  // first column of the solve
     for (int64_t t = int64_t(blockIdx.x) * 4 + w; t < total; t += int64_t(gridDim.x) * 4) {
         const int th = int(t / a.ntasks);
+        if (MODE == FIN_LEAF && a.rep && (a.leaf_phase == 0) == (a.rep[th] == th)) continue;
         const int64_t g = a.tasks[t % a.ntasks];
         const int64_t lo = a.obs_lo[g];
         const int n = int(a.obs_hi[g] - lo);
         const double* thp = a.theta + 3 * th;
         const double alpha = thp[0], inv_beta = 1.0 / thp[1], tau = thp[2];
         double* Fr = a.F + th * a.F_stride + lo * a.WFs;
+        // rows read: [V | z] of the representative for a theta that shares it
+        const double* Fs = (MODE == FIN_LEAF && a.rep && a.leaf_phase == 0) ? a.F + a.rep[th] * a.F_stride + lo * a.WFs : Fr;
         // product over K columns: 16x16 lower tiles (rt >= ct)
         v4d acc[NR * (NR + 1) / 2];
 #pragma unroll
@@ -136,7 +140,7 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 3 : 1)) k_small(KArgs a) {
                     const int row = 16 * rt + lr;
                     fr[d][rt] = v4d{0.0, 0.0, 0.0, 0.0};
                     if (row < n && kb + 16 * d < K)
-                        fr[d][rt] = *reinterpret_cast<const v4d*>(Fr + int64_t(row) * a.WFs + kc0 + kb + 16 * d + 4 * lg);
+                        fr[d][rt] = *reinterpret_cast<const v4d*>(Fs + int64_t(row) * a.WFs + kc0 + kb + 16 * d + 4 * lg);
                 }
 #pragma unroll
             for (int d = 0; d < KD; ++d)
@@ -198,7 +202,7 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 3 : 1)) k_small(KArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < NMAX / 4; ++ks) {
                     const int kk = 4 * ks + lg, c = c0 + 16 * d + lr;
-                    bv[d][ks] = ldg0(Fr, int64_t(kk) * a.WFs + c, kk < n && c < a.WF);
+                    bv[d][ks] = ldg0(Fs, int64_t(kk) * a.WFs + c, kk < n && c < a.WF);
                 }
 #pragma unroll
             for (int d = 0; d < CD; ++d) {
@@ -260,6 +264,7 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
     double* Ag = a.scratch + int64_t(blockIdx.x) * a.scratch_stride;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         const int th = int(t / a.ntasks);
+        if (MODE == FIN_LEAF && a.rep && (a.leaf_phase == 0) == (a.rep[th] == th)) continue;  // uniform
         const int64_t g = a.tasks[t % a.ntasks];
         const int64_t lo = a.obs_lo[g];
         const int n = int(a.obs_hi[g] - lo);
@@ -267,6 +272,10 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
         const double* thp = a.theta + 3 * th;
         const double alpha = thp[0], inv_beta = 1.0 / thp[1], tau = thp[2];
         double* Fr = a.F + th * a.F_stride + lo * a.WFs;
+        // rows read at their first touch (the matrix, and every row in the
+        // first block step): [V | z] of the representative for a theta that
+        // shares it, else the theta's own
+        const double* Fs = (MODE == FIN_LEAF && a.rep && a.leaf_phase == 0) ? a.F + a.rep[th] * a.F_stride + lo * a.WFs : Fr;
         const double* px = a.x + lo;
         const double* py = a.y + lo;
         if (MODE == FIN_LEAF)
@@ -277,7 +286,7 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
         for (int st = ns - 1 - w; st >= 0; st -= 4) {
             const int r = 16 * st + lr;
             const bool rok = r < n;
-            const double* ra = Fr + (rok ? int64_t(r) * a.WFs : 0) + cm;
+            const double* ra = Fs + (rok ? int64_t(r) * a.WFs : 0) + cm;
             for (int cg = 0; cg <= st; cg += 4) {
                 v4d acc[4];
 #pragma unroll
@@ -288,7 +297,7 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
                 for (int c = 0; c < 4; ++c) {
                     const int cc = 16 * (cg + c) + lr;
                     cok[c] = cg + c <= st && cc < n;
-                    cb[c] = Fr + (cok[c] ? int64_t(cc) * a.WFs : 0) + cm;
+                    cb[c] = Fs + (cok[c] ? int64_t(cc) * a.WFs : 0) + cm;
                 }
                 for (int k0 = 0; k0 < K; k0 += 32) {
                     v4d av[2], bv[2][4];
@@ -455,16 +464,17 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
                 // masked lane reads the region's first element instead (the
                 // base itself may lie past the region's last row)
                 const int64_t s4 = int64_t(4) * a.WFs;
+                const double* Fx = j0 == 0 ? Fs : Fr;  // rows not yet written by this task
                 auto load_k = [&](int sl, v4d (&v)[4]) {
                     const int c = xc0 + 16 * sl + lr;
                     const bool cok = sl < nsl && c < a.WF;
-                    const double* b = Fr + int64_t(j0 + lg) * a.WFs + c;
+                    const double* b = Fx + int64_t(j0 + lg) * a.WFs + c;
 #pragma unroll
                     for (int t2 = 0; t2 < 4; ++t2)
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const bool ok = cok && 16 * t2 + lg + 4 * i < jb;
-                            const double vv = *(ok ? b + (4 * t2 + i) * s4 : Fr);
+                            const double vv = *(ok ? b + (4 * t2 + i) * s4 : Fx);
                             v[t2][i] = ok ? vv : 0.0;
                         }
                 };
@@ -478,12 +488,13 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
                     double* bk = Fr + int64_t(j0 + lg) * a.WFs + c;  // rows of block k (stores only when valid)
                     double* b1 = Fr + int64_t(r1 + lg) * a.WFs + c;  // rows of the first chunk
                     if (chunk1) {
+                        const double* b1x = Fx + int64_t(r1 + lg) * a.WFs + c;
 #pragma unroll
                         for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
                                 const bool ok = cok && r1 + 16 * rt + lg + 4 * i < n;
-                                const double vv = *(ok ? b1 + (4 * rt + i) * s4 : Fr);
+                                const double vv = *(ok ? b1x + (4 * rt + i) * s4 : Fx);
                                 xr[rt][i] = ok ? vv : 0.0;
                             }
                     }
@@ -544,7 +555,7 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const int rr = r0 + 16 * rt + lg + 4 * i;
-                            o[i] = ldg0(Fr, int64_t(rr) * a.WFs + c, cok && rr < n);
+                            o[i] = ldg0(j0 == 0 ? Fs : Fr, int64_t(rr) * a.WFs + c, cok && rr < n);
                         }
 #pragma unroll
                         for (int t2 = 0; t2 < 4; ++t2)

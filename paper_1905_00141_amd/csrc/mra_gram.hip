@@ -520,7 +520,36 @@ __global__ void k_fill_int(int* p, int64_t n, int v) {
         p[i] = v;
 }
 
+// Representatives of a chunk's theta: rep[i] = the first j <= i with the same
+// alpha and range (the prior does not involve the nugget).
+__global__ void k_rep(const double* theta, int nb, int* rep) {
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        int r = i;
+        for (int j = 0; j < i; ++j)
+            if (theta[3 * j] == theta[3 * i] && theta[3 * j + 1] == theta[3 * i + 1]) {
+                r = j;
+                break;
+            }
+        rep[i] = r;
+    }
+}
+
+// A failed prior factor of a representative fails the theta that share it.
+__global__ void k_rep_status(const int* rep, int nb, int* status) {
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+        if (rep[i] != i && status[i] == 0) status[i] = status[rep[i]];
+}
+
 // ---- host-side launchers
+
+hipError_t launch_rep(const double* theta, int nb, int* rep, hipStream_t st) {
+    hipLaunchKernelGGL(k_rep, dim3(1), dim3(64), 0, st, theta, nb, rep);
+    return hipGetLastError();
+}
+hipError_t launch_rep_status(const int* rep, int nb, int* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_rep_status, dim3(1), dim3(64), 0, st, rep, nb, status);
+    return hipGetLastError();
+}
 
 hipError_t launch_gram_panel(const KArgs& a, int grid, hipStream_t st) {
     hipLaunchKernelGGL(k_gram_panel, dim3(grid), dim3(NT), 0, st, a);

@@ -46,6 +46,15 @@ struct KArgs {
     double* dval;  int64_t d_stride;
     double* scratch; int64_t scratch_stride;
     int* status;              // per theta: 0, or 1 + global index of the failing region
+    // Theta that share alpha and range share the prior (levels 1..M-1 and the
+    // observations' whitened rows do not involve the nugget).  rep (per theta
+    // of the chunk, or null for no sharing) is the first theta of the chunk
+    // with the same alpha and range: the prior kernels run for such
+    // representatives only.  leaf_phase, for the finest-level finishers when
+    // rep is set: 0 = the other theta, reading [V | z] from their
+    // representative's rows; 1 = the representatives, in place.
+    const int* rep;
+    int leaf_phase;
     const int* tasks;         // region list of this launch
     int64_t ntasks;           // regions per theta
     int level;                // level (1-based) of this launch
