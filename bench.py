@@ -183,6 +183,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="run the execution-plan autotuner on 4 of the theta before timing (about a minute; "
                          "on this workload it keeps the default plan)")
+    ap.add_argument("--no-share", action="store_true",
+                    help="compute the prior for every theta (no sharing between theta with the same alpha and range)")
     ap.add_argument("--no-mle", action="store_true",
                     help="skip the MLE searches that follow the timed steps by default on the same tree (32x32 "
                          "profiled grid, Nelder-Mead, trust region, the surrogate's sequential design; exact-"
@@ -215,6 +217,12 @@ def main():
     log(f"[bench] data {cfg['name']} generated in {time.time() - t0:.1f} s")
     t0 = time.time()
     tree = mra.Tree(cfg["x"], cfg["y"], cfg["z"], J=cfg["J"], r=cfg["r"], M=cfg["M"], domain=cfg["domain"])
+    # the grid is range-major with nt nuggets per range: the prior (alpha and
+    # range only) is shared within each group, so whole groups go to a chunk
+    if not args.no_share:
+        tree.set_chunk_multiple(nt)
+    else:
+        os.environ["MRA_SHARE_PRIOR"] = "0"
     info = tree.info
     log(f"[bench] tree built in {time.time() - t0:.1f} s: n_used {info['n_used']}, leaves "
         f"{info['leaf_min']}..{info['leaf_max']} obs, {info['n_gram_regions']} Gram-form regions")
@@ -315,6 +323,8 @@ def main():
             "r_hat": int(info["r_hat"]), "n_theta": int(B), "family": "matern", "nu": 1.5,
             "leaf_obs_min": int(info["leaf_min"]), "leaf_obs_max": int(info["leaf_max"]),
             "whole_path_tflops": all_flops / (ms_step * 1e-3) / 1e12,
+            "prior_shared": not args.no_share,
+            "distinct_alpha_range": int(len({(float(a), float(b)) for a, b, _ in cfg["theta"]})),
             "plan": None if tune is None else {"fold_max": tune["fold_max"], "small_max": tune["small_max"],
                                                "tile": tune["tile"]},
         },

@@ -261,6 +261,23 @@ int mra_set_plan(mra_tree *tree, const int64_t *fold_max, int small_max);
 int mra_set_tile_shapes(mra_tree *tree, const int32_t *tile);
 
 /*
+ * Parameter vectors that share alpha and the range share the prior (every
+ * level above the finest and the observations' whitened rows: the nugget
+ * enters the finest level only, Sec. 1.1).  Within each chunk of theta that
+ * device memory allows, mra_loglik computes the prior once per distinct
+ * (alpha, range) -- found on the device, so captured graphs follow new values
+ * -- and the other theta of the chunk reuse it, with results identical to
+ * evaluating each theta alone.  A caller whose theta come in consecutive
+ * groups of g with the same (alpha, range) (for instance a grid with g
+ * nuggets per range) calls this with multiple = g, so that chunk sizes are
+ * multiples of g and no group is split between chunks (multiple = 1: no
+ * rounding, the default).  The environment variable MRA_SHARE_PRIOR=0
+ * switches the sharing off.  Returns MRA_EINVAL for multiple < 1.  Same
+ * workspace rules as mra_set_plan.
+ */
+int mra_set_chunk_multiple(mra_tree *tree, int64_t multiple);
+
+/*
  * Optional per-launch timing, for measurement.  While enabled, every kernel
  * launch of mra_loglik is bracketed by HIP events on the caller's stream, or,
  * with only_kernel non-NULL, only the launches of that kernel at only_level

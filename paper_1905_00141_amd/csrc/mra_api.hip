@@ -168,6 +168,7 @@ struct mra_tree {
     Plan lik;  // plan of the likelihood
     int64_t leaf_min = 0, leaf_max = 0;
     int64_t leaf_hist[16] = {0};
+    int64_t chunk_multiple = 1;  // theta per chunk rounded down to a multiple of this
     void* ws = nullptr;  // Workspace*, owned
     ~mra_tree();
 };
@@ -810,8 +811,10 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
     const double budget = 0.6 * double(free_b) / 8.0;  // doubles
     const int64_t nslot = std::min<int64_t>(2048, std::max<int64_t>(1, int64_t(0.2 * budget / double(scratch_per))));
     const double left = budget - double(nslot) * double(scratch_per);
-    const int64_t Bc = std::min<int64_t>(std::max<int64_t>(B, 1), int64_t(left / double(per_theta)));
+    int64_t Bc = std::min<int64_t>(std::max<int64_t>(B, 1), int64_t(left / double(per_theta)));
     if (Bc < 1) return fail(MRA_ENOMEM, "not enough device memory for one theta");
+    // whole groups of theta that share a prior per chunk (when more than one fits)
+    if (Bc < B && Bc >= t->chunk_multiple) Bc -= Bc % t->chunk_multiple;
     const int64_t capB = std::max<int64_t>(B, 64);
     auto al = [](void** p, size_t bytes) { return hipMalloc(p, std::max<size_t>(bytes, 8)) == hipSuccess; };
     if (!al(reinterpret_cast<void**>(&w.vst), size_t(Bc) * pl.vst_size * 8) ||
@@ -1155,6 +1158,15 @@ extern "C" int mra_set_tile_shapes(mra_tree* t, const int32_t* tile) {
         t->opts.tile[m] = int8_t(v);
     }
     return replan(t);
+}
+
+extern "C" int mra_set_chunk_multiple(mra_tree* t, int64_t multiple) {
+    if (!t) return fail(MRA_EINVAL, "NULL tree");
+    if (multiple < 1) return fail(MRA_EINVAL, "the chunk multiple must be at least 1");
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if (t->ws) static_cast<Workspace*>(t->ws)->release();
+    t->chunk_multiple = multiple;
+    return MRA_OK;
 }
 
 extern "C" int mra_set_plan(mra_tree* t, const int64_t* fold_max, int small_max) {

@@ -27,7 +27,7 @@ EXPORTED = ["mra_build_tree", "mra_loglik", "mra_loglik_terms", "mra_loglik_leve
             "mra_loglik_noalloc",
             "mra_predict", "mra_free_tree", "mra_last_error",
             "mra_tree_info", "mra_tree_arrays", "mra_profile_enable", "mra_profile_read",
-            "mra_autotune", "mra_set_plan", "mra_set_tile_shapes", "mra_bench_mfma_f64",
+            "mra_autotune", "mra_set_plan", "mra_set_tile_shapes", "mra_set_chunk_multiple", "mra_bench_mfma_f64",
             "mra_mlp_create", "mra_mlp_set_scaling", "mra_mlp_forward", "mra_mlp_loss_grad",
             "mra_mlp_train_step", "mra_mlp_get_params", "mra_mlp_free"]
 MLP_WIDTH = 128
@@ -97,6 +97,8 @@ def load_library(path: str = LIB_PATH):
     L.mra_set_plan.restype = C.c_int
     L.mra_set_tile_shapes.argtypes = [vp, vp]
     L.mra_set_tile_shapes.restype = C.c_int
+    L.mra_set_chunk_multiple.argtypes = [vp, i64]
+    L.mra_set_chunk_multiple.restype = C.c_int
     L.mra_bench_mfma_f64.argtypes = [i64, C.POINTER(C.c_double)]
     L.mra_bench_mfma_f64.restype = C.c_int
     f32 = C.c_float
@@ -262,6 +264,11 @@ class Tree:
         return dict(fold_max=[int(r.fold_max[i]) for i in range(r.levels - 1)], small_max=int(r.small_max),
                     tile=[int(r.tile[i]) for i in range(r.levels - 1)],
                     ms_before=r.ms_before, ms_after=r.ms_after, trials=int(r.trials))
+
+    def set_chunk_multiple(self, multiple):
+        """Round the theta per chunk down to a multiple of `multiple`: for
+        theta in consecutive groups that share alpha and range."""
+        _check(_lib.mra_set_chunk_multiple(self._h, int(multiple)))
 
     def set_tile_shapes(self, tile=None):
         """Schur-block tile shape per level 1 .. M-1 (-1 default, 0 64 x 64, 1 128 x 128)."""

@@ -112,3 +112,13 @@ def test_failed_prior_fails_every_theta_of_its_group(mra):
     with pytest.raises(mra.MraError) as e:
         t.status()
     assert e.value.code == mra.MRA_ENOTPD
+
+
+def test_chunk_multiple(mra, case):
+    t = _tree(mra, case)
+    ref = t.loglik(THETAS, "matern", 1.5)
+    t.set_chunk_multiple(3)
+    assert np.array_equal(t.loglik(THETAS, "matern", 1.5), ref)
+    with pytest.raises(mra.MraError) as e:
+        t.set_chunk_multiple(0)
+    assert e.value.code == mra.MRA_EINVAL
