@@ -119,6 +119,8 @@ struct Plan {
     std::vector<int> leaf_tasks;                    // leaves with > 64 observations
     std::vector<int> small_tasks[3];                // leaves with <= 16, 17..32, 33..64 observations
     std::vector<int> chain_obs_tasks;               // level-(M-1) regions with observations
+    std::vector<int64_t> s0_off;                    // per leaf: offset of its C - V V^T (theta with a shared prior)
+    int64_t s0_size = 1;
     int64_t scratch_leaf = 0, scratch_fold = 0;     // doubles per workgroup slot
     int root_gram = 0;
     int64_t n_gram = 0;
@@ -127,6 +129,7 @@ struct Plan {
     int64_t *d_vst_off = nullptr, *d_gram_off = nullptr;
     std::vector<int*> d_prior, d_factor, d_gramt, d_fsmall[3];
     int *d_leaf = nullptr, *d_small[3] = {nullptr, nullptr, nullptr}, *d_chain_obs = nullptr;
+    int64_t* d_s0_off = nullptr;
     // algorithmic FP64 flops of one theta
     std::vector<double> fl_chain, fl_pfin, fl_factor, fl_gram, fl_gtile, fl_fsmall[3];
     // knot-space blocks of level m staged through LDS in 128 x 128 super-blocks
@@ -135,9 +138,11 @@ struct Plan {
     // at a median of 0)
     std::vector<int8_t> gtile_super;
     double fl_chain_obs = 0.0, fl_leaf = 0.0, fl_small[3] = {0.0, 0.0, 0.0};
+    // the part of fl_leaf / fl_small that forms C - V V^T: (M-1) n^2 p
+    double fl_leaf_s = 0.0, fl_small_s[3] = {0.0, 0.0, 0.0};
 
     ~Plan() {
-        void* ps[] = {d_form, d_vst_off, d_gram_off, d_leaf, d_small[0], d_small[1], d_small[2], d_chain_obs};
+        void* ps[] = {d_form, d_vst_off, d_gram_off, d_leaf, d_small[0], d_small[1], d_small[2], d_chain_obs, d_s0_off};
         for (void* p : ps)
             if (p) (void)hipFree(p);
         for (auto* v : {&d_prior, &d_factor, &d_gramt, &d_fsmall[0], &d_fsmall[1], &d_fsmall[2]})
@@ -235,11 +240,15 @@ static void plan_flops(const HostTree& h, Plan& t) {
         const double n = double(h.obs_hi[g] - h.obs_lo[g]);
         return L * n * n * p + n * n * n / 3.0 + n * n * (L * p + 1);
     };
-    t.fl_leaf = 0.0;
-    for (int g : t.leaf_tasks) t.fl_leaf += fl(g);
+    auto fls = [&](int g) {
+        const double n = double(h.obs_hi[g] - h.obs_lo[g]);
+        return L * n * n * p;
+    };
+    t.fl_leaf = t.fl_leaf_s = 0.0;
+    for (int g : t.leaf_tasks) t.fl_leaf += fl(g), t.fl_leaf_s += fls(g);
     for (int q = 0; q < 3; ++q) {
-        t.fl_small[q] = 0.0;
-        for (int g : t.small_tasks[q]) t.fl_small[q] += fl(g);
+        t.fl_small[q] = t.fl_small_s[q] = 0.0;
+        for (int g : t.small_tasks[q]) t.fl_small[q] += fl(g), t.fl_small_s[q] += fls(g);
     }
 }
 
@@ -313,8 +322,12 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
     }
     t.vst_size = std::max<int64_t>(vo, 1);
     t.gram_size = std::max<int64_t>(go, 1);
+    t.s0_off.assign(size_t(h.lvl_start[M] - h.lvl_start[M - 1]), 0);
+    int64_t s0 = 0;
     for (int64_t g = h.lvl_start[M - 1]; g < h.lvl_start[M]; ++g) {
         const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
+        t.s0_off[size_t(g - h.lvl_start[M - 1])] = s0;
+        s0 += nc * ((nc + 3) & ~int64_t(3));
         if (nc > smax) {
             t.leaf_tasks.push_back(int(g));
             t.scratch_leaf = std::max(t.scratch_leaf, nc * ((nc + 3) & ~int64_t(3)));
@@ -326,6 +339,7 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
             t.small_tasks[0].push_back(int(g));
         }
     }
+    t.s0_size = std::max<int64_t>((s0 + 31) & ~int64_t(31), 1);
     t.root_gram = (M > 1 && t.form[0] == FOLD_GRAM && t.gram_off[0] >= 0) ? 1 : 0;
     plan_flops(h, t);
     if (opts)
@@ -335,7 +349,8 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
     if ((rc = upload(&t.d_vst_off, t.vst_off)) || (rc = upload(&t.d_gram_off, t.gram_off)) ||
         (rc = upload(&t.d_form, t.form)) || (rc = upload(&t.d_leaf, t.leaf_tasks)) ||
         (rc = upload(&t.d_small[0], t.small_tasks[0])) || (rc = upload(&t.d_small[1], t.small_tasks[1])) ||
-        (rc = upload(&t.d_small[2], t.small_tasks[2])) || (rc = upload(&t.d_chain_obs, t.chain_obs_tasks))) {
+        (rc = upload(&t.d_small[2], t.small_tasks[2])) || (rc = upload(&t.d_chain_obs, t.chain_obs_tasks)) ||
+        (rc = upload(&t.d_s0_off, t.s0_off))) {
         err = "device allocation failed for the execution plan";
         return rc;
     }
@@ -645,6 +660,9 @@ static KArgs base_args(const mra_tree* t, const Plan& pl, int smooth) {
     a.zero_nugget = (t->flags & MRA_ALLOW_ZERO_NUGGET) ? 1 : 0;
     a.rep = nullptr;
     a.leaf_phase = -1;
+    a.S0 = nullptr;
+    a.S0_off = pl.d_s0_off;
+    a.S0_stride = pl.s0_size;
     return a;
 }
 
@@ -684,14 +702,17 @@ static hipError_t enqueue_leaves(const mra_tree* t, const Plan& pl, KArgs a, int
     for (int q = 0; q < 3; ++q) {
         a.tasks = pl.d_small[q];
         a.ntasks = int64_t(pl.small_tasks[q].size());
-        if (a.ntasks > 0 && (e = timed(6, M, pl.fl_small[q] * nth, st, [&] {
+        const double fq = a.leaf_phase == 2 ? pl.fl_small_s[q] : a.leaf_phase >= 0 ? pl.fl_small[q] - pl.fl_small_s[q]
+                                                                                    : pl.fl_small[q];
+        if (a.ntasks > 0 && (e = timed(6, M, fq * nth, st, [&] {
                                  return launch_small(a, 16 << q, 0, int(std::min<int64_t>(a.ntasks * nb, 1 << 18)), st);
                              })))
             return e;
     }
     a.tasks = pl.d_leaf;
     a.ntasks = int64_t(pl.leaf_tasks.size());
-    if (a.ntasks > 0 && (e = timed(2, M, pl.fl_leaf * nth, st, [&] {
+    const double fl = a.leaf_phase == 2 ? pl.fl_leaf_s : a.leaf_phase >= 0 ? pl.fl_leaf - pl.fl_leaf_s : pl.fl_leaf;
+    if (a.ntasks > 0 && (e = timed(2, M, fl * nth, st, [&] {
                              return launch_leaf(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st);
                          })))
         return e;
@@ -750,6 +771,7 @@ struct Workspace {
     double *th = nullptr, *out = nullptr, *ld = nullptr, *q = nullptr;
     int* status = nullptr;
     int* rep = nullptr;  // per theta of a chunk: its representative (shared prior)
+    double* S0 = nullptr;  // per theta of a chunk: C - V V^T of every leaf (shared prior)
     int64_t Bc = 0, nslot = 0, scratch_per = 0, cap_B = 0;
     bool mem_limited = false;  // Bc was capped by device memory, not by the request
     hipEvent_t done = nullptr;
@@ -769,9 +791,9 @@ struct Workspace {
         for (void* p : {static_cast<void*>(vst), static_cast<void*>(F), static_cast<void*>(gram),
                         static_cast<void*>(dval), static_cast<void*>(scratch), static_cast<void*>(th),
                         static_cast<void*>(out), static_cast<void*>(ld), static_cast<void*>(q),
-                        static_cast<void*>(status), static_cast<void*>(rep)})
+                        static_cast<void*>(status), static_cast<void*>(rep), static_cast<void*>(S0)})
             if (p) (void)hipFree(p);
-        vst = F = gram = dval = scratch = th = out = ld = q = nullptr;
+        vst = F = gram = dval = scratch = th = out = ld = q = S0 = nullptr;
         status = rep = nullptr;
         Bc = nslot = cap_B = 0;
         used = false;
@@ -801,7 +823,7 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
     const HostTree& h = t->h;
     const Plan& pl = t->lik;
     const int64_t F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
-    const int64_t per_theta = pl.vst_size + F_stride + pl.gram_size + h.nreg;
+    const int64_t per_theta = pl.vst_size + F_stride + pl.gram_size + h.nreg + pl.s0_size;
     const int64_t scratch_per = (std::max<int64_t>({pl.scratch_leaf, pl.scratch_fold, 1}) + 31) & ~int64_t(31);
     // reuse when the buffers hold enough theta per chunk (or could not hold more)
     if (w.Bc > 0 && w.cap_B >= B && (w.Bc >= B || w.mem_limited)) return MRA_OK;
@@ -824,6 +846,7 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
         !al(reinterpret_cast<void**>(&w.scratch), size_t(nslot) * scratch_per * 8) ||
         !al(reinterpret_cast<void**>(&w.status), size_t(capB) * sizeof(int)) ||
         !al(reinterpret_cast<void**>(&w.rep), size_t(capB) * sizeof(int)) ||
+        !al(reinterpret_cast<void**>(&w.S0), size_t(Bc) * pl.s0_size * 8) ||
         !al(reinterpret_cast<void**>(&w.th), size_t(capB) * 3 * 8) ||
         !al(reinterpret_cast<void**>(&w.out), size_t(capB) * 8) ||
         !al(reinterpret_cast<void**>(&w.ld), size_t(capB) * 8) ||
@@ -855,7 +878,7 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
 // captured graph stays valid for new values in the same buffer.
 static hipError_t enqueue_loglik(const mra_tree* t, int64_t Bc, int64_t nslot, KArgs a, const double* d_th,
                                  double* d_out, double* d_ld, double* d_q, int* status, int64_t B, hipStream_t st,
-                                 double* d_lev = nullptr, int* rep_buf = nullptr) {
+                                 double* d_lev = nullptr, int* rep_buf = nullptr, double* s0_buf = nullptr) {
     const HostTree& h = t->h;
     const Plan& pl = t->lik;
     hipError_t e;
@@ -874,7 +897,7 @@ static hipError_t enqueue_loglik(const mra_tree* t, int64_t Bc, int64_t nslot, K
         a.out_ld = d_ld ? d_ld + b0 : nullptr;
         a.out_q = d_q ? d_q + b0 : nullptr;
         a.out_lev = d_lev ? d_lev + b0 * h.M : nullptr;
-        const bool share = rep_buf && nb > 1 && h.M > 1;
+        const bool share = rep_buf && s0_buf && nb > 1 && h.M > 1;
         double nrep = nb;  // representatives (the profiler's flop count; eager launches only)
         if (share && prof) {
             std::vector<double> th(size_t(3) * nb);
@@ -898,11 +921,15 @@ static hipError_t enqueue_loglik(const mra_tree* t, int64_t Bc, int64_t nslot, K
         if ((e = enqueue_prior(t, pl, a, nb, st, nrep))) return e;
         if (share) {
             if ((e = launch_rep_status(a.rep, nb, a.status, st))) return e;
+            a.S0 = s0_buf;
+            a.leaf_phase = 2;  // C - V V^T of every leaf, once per representative
+            if ((e = enqueue_leaves(t, pl, a, nb, nslot, st, nrep))) return e;
             a.leaf_phase = 0;  // the theta that share a prior, from their representative's rows
             if ((e = enqueue_leaves(t, pl, a, nb, nslot, st, nb - nrep))) return e;
             a.leaf_phase = 1;  // then the representatives, in place
             if ((e = enqueue_leaves(t, pl, a, nb, nslot, st, nrep))) return e;
             a.rep = nullptr;
+            a.S0 = nullptr;
             a.leaf_phase = -1;
         } else if ((e = enqueue_leaves(t, pl, a, nb, nslot, st))) {
             return e;
@@ -986,7 +1013,7 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
             hipGraphExec_t ge = nullptr;
             HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             const hipError_t ce =
-                enqueue_loglik(t, w.Bc, w.nslot, a, d_th, d_out, d_ld, d_q, w.status, B, st, nullptr, rep_buf);
+                enqueue_loglik(t, w.Bc, w.nslot, a, d_th, d_out, d_ld, d_q, w.status, B, st, nullptr, rep_buf, w.S0);
             const hipError_t ee = hipStreamEndCapture(st, &g);
             HIPCHK(ce);
             HIPCHK(ee);
@@ -997,7 +1024,7 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
         }
         HIPCHK(hipGraphLaunch(it->second, st));
     } else {
-        HIPCHK(enqueue_loglik(t, w.Bc, w.nslot, a, d_th, d_out, d_ld, d_q, w.status, B, st, d_lev, rep_buf));
+        HIPCHK(enqueue_loglik(t, w.Bc, w.nslot, a, d_th, d_out, d_ld, d_q, w.status, B, st, d_lev, rep_buf, w.S0));
     }
     (void)hipEventRecord(w.done, st);
     w.last = st;

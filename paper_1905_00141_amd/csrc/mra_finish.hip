@@ -124,6 +124,19 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 3 : 1)) k_small(KArgs a) {
         double* Fr = a.F + th * a.F_stride + lo * a.WFs;
         // rows read: [V | z] of the representative for a theta that shares it
         const double* Fs = (MODE == FIN_LEAF && a.rep && a.leaf_phase == 0) ? a.F + a.rep[th] * a.F_stride + lo * a.WFs : Fr;
+        // a shared prior: C - V V^T (pitch n rounded up to 4), formed once per
+        // representative (phase 2) and taken from there by its group
+        const bool s0_build = MODE == FIN_LEAF && a.S0 && a.leaf_phase == 2;
+        const bool s0_use = MODE == FIN_LEAF && a.S0 && a.leaf_phase != 2;
+        double* S0p = (MODE == FIN_LEAF && a.S0) ? a.S0 + a.rep[th] * a.S0_stride + a.S0_off[g - a.lvl[M - 1]] : nullptr;
+        const int lds = (n + 3) & ~3;
+        if (s0_use) {
+            for (int e = lane; e < NMAX * NMAX; e += 64) {
+                const int r = e / NMAX, c = e % NMAX;
+                if (c <= r)
+                    Tw[r * LDT + c] = (r < n && c < n) ? S0p[r * lds + c] + (r == c ? tau : 0.0) : (r == c ? 1.0 : 0.0);
+            }
+        } else {
         // product over K columns: 16x16 lower tiles (rt >= ct)
         v4d acc[NR * (NR + 1) / 2];
 #pragma unroll
@@ -170,18 +183,24 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 3 : 1)) k_small(KArgs a) {
                         if (r < n && c < n) {
                             if (MODE == FIN_LEAF) {
                                 v = cov_pts(a.x[lo + r], a.y[lo + r], cx, cy, alpha, inv_beta, a.smooth) - acc[e][i];
-                                if (r == c) v += tau;
+                                if (r == c && !s0_build) v += tau;
                             } else {
                                 v = acc[e][i] + (r == c ? 1.0 : 0.0);
                             }
                         } else {
                             v = (r == c) ? 1.0 : 0.0;
                         }
-                        if (c <= r) Tw[r * LDT + c] = v;
+                        if (s0_build) {
+                            if (c <= r && r < n) S0p[r * lds + c] = v;
+                        } else if (c <= r) {
+                            Tw[r * LDT + c] = v;
+                        }
                     }
                     ++e;
                 }
         }
+        }
+        if (s0_build) continue;  // phase 2 forms the matrix only
         wsync();
         // the tile is replaced by L^{-1}
         double ldv = 0.0;
@@ -278,11 +297,22 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
         const double* Fs = (MODE == FIN_LEAF && a.rep && a.leaf_phase == 0) ? a.F + a.rep[th] * a.F_stride + lo * a.WFs : Fr;
         const double* px = a.x + lo;
         const double* py = a.y + lo;
-        if (MODE == FIN_LEAF)
+        // a shared prior: C - V V^T of the leaf, formed once per representative
+        // (phase 2) and taken from there by every theta of its group
+        const bool s0_build = MODE == FIN_LEAF && a.S0 && a.leaf_phase == 2;
+        const bool s0_use = MODE == FIN_LEAF && a.S0 && a.leaf_phase != 2;
+        double* S0p = (MODE == FIN_LEAF && a.S0) ? a.S0 + a.rep[th] * a.S0_stride + a.S0_off[g - a.lvl[M - 1]] : nullptr;
+        if (MODE == FIN_LEAF && !s0_build)
             for (int r = tid; r < n; r += NT) Fr[int64_t(r) * a.WFs + (a.WF - 1)] = a.z[lo + r];
         // ---- 1. the matrix: 16-row strips (round robin over the waves),
         // 64 columns (four 16 x 16 tiles) at a time, lower triangle
-        const int ns = (n + 15) / 16;
+        double* Sd = s0_build ? S0p : Ag;
+        const int ns = s0_use ? 0 : (n + 15) / 16;
+        if (s0_use) {
+            // from the group's C - V V^T, plus this theta's nugget
+            for (int r = w; r < n; r += 4)
+                for (int c = lane; c <= r; c += 64) Ag[int64_t(r) * lda + c] = S0p[int64_t(r) * lda + c] + (r == c ? tau : 0.0);
+        }
         for (int st = ns - 1 - w; st >= 0; st -= 4) {
             const int r = 16 * st + lr;
             const bool rok = r < n;
@@ -331,17 +361,18 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
                             double v;
                             if (MODE == FIN_LEAF) {
                                 v = cov_pts(px[rr], py[rr], cx, cy, alpha, inv_beta, a.smooth) - acc[c][i];
-                                if (rr == cc) v += tau;
+                                if (rr == cc && !s0_build) v += tau;
                             } else {
                                 v = acc[c][i] + (rr == cc ? 1.0 : 0.0);
                             }
-                            Ag[int64_t(rr) * lda + cc] = v;
+                            Sd[int64_t(rr) * lda + cc] = v;
                         }
                     }
                 }
             }
         }
         __syncthreads();
+        if (s0_build) continue;  // uniform: phase 2 forms the matrix only
         // ---- 2. blocked factorization and solve
         double logdet = 0.0;
         bool failed = false;

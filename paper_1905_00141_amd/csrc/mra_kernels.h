@@ -55,6 +55,12 @@ struct KArgs {
     // representative's rows; 1 = the representatives, in place.
     const int* rep;
     int leaf_phase;
+    // leaf_phase 2 (representatives): C(S, S) - V V^T of every leaf (lower,
+    // pitch n rounded up to 4) into S0 at the representative's slot; phases 0
+    // and 1 then start from it (plus the nugget) instead of forming it
+    double* S0;
+    const int64_t* S0_off;    // per leaf (index within the finest level)
+    int64_t S0_stride;        // per theta
     const int* tasks;         // region list of this launch
     int64_t ntasks;           // regions per theta
     int level;                // level (1-based) of this launch
