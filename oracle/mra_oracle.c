@@ -48,6 +48,9 @@ static int fail(int code, const char *msg) {
 /* build flags (same values as the library's) */
 #define O_ELIM_DUPLICATES (1u << 1) /* drop repeated locations, keep the first (Sec. 2.2) */
 #define O_ALLOW_ZERO_NUGGET (1u << 2) /* accept tau = 0 in the likelihood */
+/* r knots at the finest level too (Sec. 1.2, the further approximation):
+ * the finest-level remainder is represented by its knots, not kept exact */
+#define O_FURTHER_APPROX (1u << 3)
 
 typedef struct otree {
     int J, M, r, nx, ny, rhat;
@@ -631,18 +634,33 @@ static void visit(rctx *ctx, int m, int64_t k, double *A, double *w, double *du)
             return;
         }
         const double *px = t->x + o, *py = t->y + o, *pz = t->z + o;
+        const int fa = (t->flags & O_FURTHER_APPROX) != 0;
+        /* further approximation: the leaf's own knots form level M of the
+         * prior, and C_M(S,S) is replaced by B^M K_M B^M^T with
+         * B^M = C_M(S, Q_R) */
+        if (fa) {
+            prior_region(ctx, M, k);
+            if (ctx->status) { free_region(ctx, M); return; }
+        }
+        const int Lc = fa ? M : M - 1;
         double *B[O_MAXLEV + 1] = {0}, *Z[O_MAXLEV + 1] = {0};
-        for (int l = 1; l < M; l++) {
+        for (int l = 1; l <= Lc; l++) {
             B[l] = malloc(sizeof(double) * np * p);
             Z[l] = malloc(sizeof(double) * np * p);
         }
-        prior_rows(ctx, (int)np, px, py, M - 1, B, Z);
+        prior_rows(ctx, (int)np, px, py, Lc, B, Z);
         double *S = malloc(sizeof(double) * np * np);
         for (int a = 0; a < np; a++)
             for (int b = 0; b < np; b++) {
-                double s = cov(px[a], py[a], px[b], py[b], &ctx->c);
-                for (int i = 1; i < M; i++)
-                    for (int kk = 0; kk < p; kk++) s -= Z[i][(int64_t)a * p + kk] * B[i][(int64_t)b * p + kk];
+                double s;
+                if (fa) {
+                    s = 0.0;
+                    for (int kk = 0; kk < p; kk++) s += Z[M][(int64_t)a * p + kk] * B[M][(int64_t)b * p + kk];
+                } else {
+                    s = cov(px[a], py[a], px[b], py[b], &ctx->c);
+                    for (int i = 1; i < M; i++)
+                        for (int kk = 0; kk < p; kk++) s -= Z[i][(int64_t)a * p + kk] * B[i][(int64_t)b * p + kk];
+                }
                 S[(int64_t)a * np + b] = s;
             }
         /* symmetrise the rounding of the two triangles, then add the nugget */
@@ -687,7 +705,8 @@ static void visit(rctx *ctx, int m, int64_t k, double *A, double *w, double *du)
         if (ctx->pred) leaf_predict(ctx, k, np, px, py, pz, B, S);
     leaf_done:
         free(S);
-        for (int l = 1; l < M; l++) { free(B[l]); free(Z[l]); }
+        for (int l = 1; l <= Lc; l++) { free(B[l]); free(Z[l]); }
+        if (fa) free_region(ctx, M);
         return;
     }
 
@@ -871,13 +890,17 @@ static int dense_sigma_ext(const otree *t, const cpar *c, int64_t ne, const doub
                            const int64_t *eleaf, double *Sig) {
     int64_t n = t->n_used, nn = n + ne;
     int p = t->rhat, M = t->M, J = t->J;
+    /* levels with knots: 1..M-1, or 1..M under the further approximation
+     * (the observations then sit one level below the finest knots) */
+    const int fa = (t->flags & O_FURTHER_APPROX) != 0;
+    const int ML = fa ? M : M - 1, RW = M + 2;
     int64_t nk = 0;
-    for (int m = 1; m < M; m++) nk += ipow(J, m - 1) * p;
+    for (int m = 1; m <= ML; m++) nk += ipow(J, m - 1) * p;
     int64_t nU = nn + nk;
     if (nU > 12000) return fail(O_EINVAL, "dense path limited to 12000 points");
     double *ux = malloc(sizeof(double) * nU), *uy = malloc(sizeof(double) * nU);
     int *lev = malloc(sizeof(int) * nU);
-    int64_t *reg = malloc(sizeof(int64_t) * nU * (M + 1)); /* region index at each level 1..lev */
+    int64_t *reg = malloc(sizeof(int64_t) * nU * RW); /* region index at each level 1..lev */
     double *C = malloc(sizeof(double) * nU * nU);
     if (!ux || !uy || !lev || !reg || !C) {
         free(ux); free(uy); free(lev); free(reg); free(C);
@@ -886,22 +909,24 @@ static int dense_sigma_ext(const otree *t, const cpar *c, int64_t ne, const doub
     /* observations (indices 0..n-1), extra points (n..nn-1), then knots level by level */
     for (int64_t k = 0; k < t->nleaf; k++)
         for (int64_t a = t->leaf_off[k]; a < t->leaf_off[k + 1]; a++) {
-            ux[a] = t->x[a]; uy[a] = t->y[a]; lev[a] = M;
-            for (int l = 1; l <= M; l++) reg[a * (M + 1) + l] = k / ipow(J, M - l);
+            ux[a] = t->x[a]; uy[a] = t->y[a]; lev[a] = ML + 1;
+            for (int l = 1; l <= M; l++) reg[a * RW + l] = k / ipow(J, M - l);
+            reg[a * RW + M + 1] = -1 - a; /* below the finest knots every observation is alone */
         }
     for (int64_t e = 0; e < ne; e++) {
         int64_t a = n + e;
-        ux[a] = ex[e]; uy[a] = ey[e]; lev[a] = M;
-        for (int l = 1; l <= M; l++) reg[a * (M + 1) + l] = eleaf[e] / ipow(J, M - l);
+        ux[a] = ex[e]; uy[a] = ey[e]; lev[a] = ML + 1;
+        for (int l = 1; l <= M; l++) reg[a * RW + l] = eleaf[e] / ipow(J, M - l);
+        reg[a * RW + M + 1] = -1 - a;
     }
     int64_t u = nn;
-    for (int m = 1; m < M; m++)
+    for (int m = 1; m <= ML; m++)
         for (int64_t k = 0; k < ipow(J, m - 1); k++) {
             const double *b = t->box + 4 * (t->lvl_start[m - 1] + k);
             oracle_box_knots(b[0], b[1], b[2], b[3], t->r, t->offset, ux + u, uy + u);
             for (int q = 0; q < p; q++, u++) {
                 lev[u] = m;
-                for (int l = 1; l <= m; l++) reg[u * (M + 1) + l] = k / ipow(J, m - l);
+                for (int l = 1; l <= m; l++) reg[u * RW + l] = k / ipow(J, m - l);
             }
         }
     for (int64_t a = 0; a < nU; a++)
@@ -913,13 +938,13 @@ static int dense_sigma_ext(const otree *t, const cpar *c, int64_t ne, const doub
     double *G = malloc(sizeof(double) * p * p);
     int status = O_OK;
     int64_t kstart = nn;
-    for (int m = 1; m < M && !status; m++) {
+    for (int m = 1; m <= ML && !status; m++) {
         int64_t nreg_m = ipow(J, m - 1);
         for (int64_t k = 0; k < nreg_m && !status; k++) {
             for (int q = 0; q < p; q++) Qi[q] = kstart + k * p + q;
             int64_t np = 0;
             for (int64_t a = 0; a < nU; a++)
-                if (lev[a] > m && reg[a * (M + 1) + m] == k) P[np++] = a;
+                if (lev[a] > m && reg[a * RW + m] == k) P[np++] = a;
             for (int i = 0; i < p; i++)
                 for (int j = 0; j < p; j++) G[i * p + j] = C[Qi[i] * nU + Qi[j]];
             if (chol(G, p)) { status = O_ENOTPD; break; }
@@ -935,7 +960,7 @@ static int dense_sigma_ext(const otree *t, const cpar *c, int64_t ne, const doub
                     double s = 0.0;
                     for (int i = 0; i < p; i++) s += C[ia * nU + Qi[i]] * X[i * np + b];
                     if (ia < nn && ib < nn) Sig[ia * nn + ib] += s;
-                    if (reg[ia * (M + 1) + m + 1] == reg[ib * (M + 1) + m + 1])
+                    if (reg[ia * RW + m + 1] == reg[ib * RW + m + 1])
                         C[ia * nU + ib] -= s; /* becomes C_{m+1} */
                     else
                         C[ia * nU + ib] = 0.0;
@@ -944,10 +969,12 @@ static int dense_sigma_ext(const otree *t, const cpar *c, int64_t ne, const doub
         }
         kstart += nreg_m * p;
     }
-    if (!status) {
+    /* the finest level kept exact (C_M within each leaf), unless the
+     * further approximation represents it by the leaves' knots */
+    if (!status && !fa) {
         for (int64_t a = 0; a < nn; a++)
             for (int64_t b = 0; b < nn; b++)
-                if (reg[a * (M + 1) + M] == reg[b * (M + 1) + M]) Sig[a * nn + b] += C[a * nU + b];
+                if (reg[a * RW + M] == reg[b * RW + M]) Sig[a * nn + b] += C[a * nU + b];
     }
     free(P); free(Qi); free(G);
     free(ux); free(uy); free(lev); free(reg); free(C);
@@ -1042,6 +1069,7 @@ static int sort_points(const otree *t, const double *px, const double *py, int64
 /* The recursion: leaf kriging, then the fold updates of mu, H, v. */
 int oracle_mra_predict(const otree *t, int family, double nu, const double *theta, const double *px,
                        const double *py, int64_t np, double *mean, double *var) {
+    if (t->flags & O_FURTHER_APPROX) return fail(O_EINVAL, "kriging is not provided for the further approximation");
     cpar c;
     int rc = make_par(family, nu, theta, &c);
     if (rc) return rc;
@@ -1081,6 +1109,7 @@ int oracle_mra_predict(const otree *t, int family, double nu, const double *thet
  * var = Sigma(p,p) - Sigma(p,S) (Sigma(S,S) + tau I)^{-1} Sigma(S,p). */
 int oracle_dense_predict(const otree *t, int family, double nu, const double *theta, const double *px,
                          const double *py, int64_t np, double *mean, double *var) {
+    if (t->flags & O_FURTHER_APPROX) return fail(O_EINVAL, "kriging is not provided for the further approximation");
     cpar c;
     int rc = make_par(family, nu, theta, &c);
     if (rc) return rc;

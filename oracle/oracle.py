@@ -24,6 +24,7 @@ _LIB = os.path.join(_HERE, "libmra_oracle.so")
 EXP, MATERN, GAUSS = 0, 1, 2
 ELIM_DUPLICATES = 1 << 1
 ALLOW_ZERO_NUGGET = 1 << 2
+FURTHER_APPROX = 1 << 3  # r knots at the finest level too (the further approximation)
 
 
 def build(force: bool = False) -> str:

@@ -334,3 +334,81 @@ def test_more_families_M1_exact_and_recursion_vs_dense(family, nu):
         a3 = t3.loglik(th3, family, nu)[0]
         b3 = t3.dense_loglik(th3, family, nu)
         assert abs(a3 - b3) <= 1e-10 * abs(b3), (th3, a3, b3)
+
+
+# --------------------------------------------- further approximation (f4)
+
+from oracle.oracle import FURTHER_APPROX  # noqa: E402
+
+
+def test_further_approximation_M1_is_the_predictive_process():
+    """M = 1 with r knots at the finest level (Sec. 1.2): the data covariance
+    is C(S,Q) C(Q,Q)^{-1} C(Q,S) + tau I with Q the root region's knots (the
+    predictive-process form), checked against SciPy."""
+    rng = np.random.default_rng(31)
+    n = 260
+    x, y, z = rng.random(n), rng.random(n), rng.standard_normal(n)
+    th = (1.4, 0.15, 0.04)
+    dom = [0.0, 1.0, 0.0, 1.0]
+    t = Tree(x, y, z, J=4, r=16, M=1, domain=dom, flags=FURTHER_APPROX)
+    a = t.arrays()
+    qx, qy = _grid_knots_np(dom, 16)
+    Cqq = _cov_np(_dist(qx, qy, qx, qy), th[0], th[1], 1.5)
+    Csq = _cov_np(_dist(a["x"], a["y"], qx, qy), th[0], th[1], 1.5)
+    K = Csq @ np.linalg.solve(Cqq, Csq.T) + th[2] * np.eye(n)
+    ref = multivariate_normal(mean=np.zeros(n), cov=K).logpdf(a["z"])
+    assert abs(t.loglik(th, MATERN, 1.5)[0] - ref) <= 1e-11 * abs(ref)
+    assert abs(t.dense_loglik(th, MATERN, 1.5) - ref) <= 1e-11 * abs(ref)
+
+
+@pytest.mark.parametrize("nu", [0.5, 1.5])
+def test_further_approximation_M2_closed_form(nu):
+    """M = 2 with knots at the leaves: Sigma = C(.,Q) C(Q,Q)^{-1} C(Q,.) with
+    Q the root knots, plus, inside each leaf l, C_2(., Q_l) C_2(Q_l,Q_l)^{-1}
+    C_2(Q_l, .) with C_2 = C - C(.,Q) C(Q,Q)^{-1} C(Q,.) (no exact
+    remainder at the finest level)."""
+    rng = np.random.default_rng(32)
+    n = 240
+    x, y, z = rng.random(n), rng.random(n), rng.standard_normal(n)
+    th = (1.1, 0.2, 0.05)
+    dom = [0.0, 1.0, 0.0, 1.0]
+    t = Tree(x, y, z, J=4, r=9, M=2, domain=dom, flags=FURTHER_APPROX)
+    a = t.arrays()
+    sx, sy = a["x"], a["y"]
+    qx, qy = _grid_knots_np(dom, 9)
+    C = lambda ax, ay, bx, by: _cov_np(_dist(ax, ay, bx, by), th[0], th[1], nu)
+    Cqq_inv = np.linalg.inv(C(qx, qy, qx, qy))
+    def C2(ax, ay, bx, by):
+        return C(ax, ay, bx, by) - C(ax, ay, qx, qy) @ Cqq_inv @ C(qx, qy, bx, by)
+    ref = C(sx, sy, qx, qy) @ Cqq_inv @ C(qx, qy, sx, sy)
+    boxes = [[0, .5, 0, .5], [.5, 1, 0, .5], [0, .5, .5, 1], [.5, 1, .5, 1]]
+    leaf = (sx >= 0.5).astype(int) + 2 * (sy >= 0.5).astype(int)
+    for l, b in enumerate(boxes):
+        kx, ky = _grid_knots_np(b, 9)
+        i = np.flatnonzero(leaf == l)
+        ref[np.ix_(i, i)] += C2(sx[i], sy[i], kx, ky) @ np.linalg.solve(C2(kx, ky, kx, ky), C2(kx, ky, sx[i], sy[i]))
+    S = t.dense_sigma(th, MATERN, nu)
+    np.testing.assert_allclose(S, ref, rtol=0, atol=1e-11 * th[0])
+    K = ref + th[2] * np.eye(n)
+    ll = multivariate_normal(mean=np.zeros(n), cov=K).logpdf(a["z"])
+    assert abs(t.loglik(th, MATERN, nu)[0] - ll) <= 1e-10 * abs(ll)
+
+
+@pytest.mark.parametrize("J,M,r,n,cluster,nu", [(4, 3, 16, 700, True, 1.5), (4, 4, 9, 800, False, 0.5),
+                                                (2, 4, 16, 500, True, 1.5), (4, 3, 30, 600, True, 0.5)])
+def test_further_approximation_recursion_matches_dense_definition(J, M, r, n, cluster, nu):
+    c = synth.small_case(200 + n + M, n, J=J, r=r, M=M, cluster=cluster, nu=nu)
+    t = Tree(c["x"], c["y"], c["z"], J=J, r=r, M=M, flags=FURTHER_APPROX)
+    e = Tree(c["x"], c["y"], c["z"], J=J, r=r, M=M)
+    for th in [(1.0, 0.05, 0.05), (2.5, 0.3, 0.01), (0.7, 0.02, 0.1)]:
+        a = t.loglik(th, MATERN, nu)[0]
+        b = t.dense_loglik(th, MATERN, nu)
+        assert abs(a - b) <= 1e-11 * abs(b), (th, a, b)
+        assert a != e.loglik(th, MATERN, nu)[0]  # a different covariance from the exact finest level
+
+
+def test_further_approximation_has_no_kriging():
+    c = synth.small_case(5, 300, M=3)
+    t = Tree(c["x"], c["y"], c["z"], J=4, r=16, M=3, flags=FURTHER_APPROX)
+    with pytest.raises(OracleError):
+        t.predict((1.0, 0.1, 0.05), np.array([0.5]), np.array([0.5]), MATERN, 0.5)
