@@ -54,6 +54,10 @@ typedef struct mra_tree mra_tree;
 #define MRA_ELIM_DUPLICATES (1u << 1)    /* drop repeated locations, keep the first (Sec. 2.2,
                                             ELIMINATION_DUPLICATES_FLAG) */
 #define MRA_ALLOW_ZERO_NUGGET (1u << 2)  /* mra_loglik accepts tau = 0 (noise-free data) */
+#define MRA_FURTHER_APPROX (1u << 3)     /* r knots at the finest level too (Sec. 1.2, the further
+                                            approximation): the finest-level remainder of each leaf is
+                                            represented by its knots' predictive process instead of
+                                            being kept exact; mra_predict refuses such a tree */
 #define MRA_FOLD_GRAM (1u << 4)    /* fold every region in knot space (Gram form) */
 #define MRA_FOLD_FACTOR (1u << 5)  /* fold in observation space wherever scratch allows */
 

@@ -170,6 +170,7 @@ struct mra_tree {
     int64_t* d_orig = nullptr;  // input index of each grouped observation (GPU-built trees)
     int64_t *d_obs_lo = nullptr, *d_obs_hi = nullptr;
     int WF = 1, WFs = 4;
+    int fa_cols = 0;  // further approximation: columns before column 0 of an F row (the leaf's own knots)
     Plan lik;  // plan of the likelihood
     int64_t leaf_min = 0, leaf_max = 0;
     int64_t leaf_hist[16] = {0};
@@ -192,11 +193,13 @@ struct mra_tree {
 //                          with K the rows of the region's observation-space
 //                          children, D = m p + 1, Dt = D - p, Ds = (m-1) p
 //                          (knot-space children contribute additions only)
-static void plan_flops(const HostTree& h, Plan& t) {
+// With the further approximation (fa) the leaves have a prior too (level M)
+// and the observation rows one more level: chain n p^2 M^2, leaf matrix n^2 p.
+static void plan_flops(const HostTree& h, Plan& t, bool fa) {
     const int M = h.M;
     const double p = h.rhat;
-    t.fl_chain.assign(M, 0.0);
-    t.fl_pfin.assign(M, 0.0);
+    t.fl_chain.assign(M + 1, 0.0);
+    t.fl_pfin.assign(M + 1, 0.0);
     t.fl_factor.assign(M, 0.0);
     t.fl_gram.assign(M, 0.0);
     t.fl_gtile.assign(M, 0.0);
@@ -234,15 +237,20 @@ static void plan_flops(const HostTree& h, Plan& t) {
             t.gtile_super[m] = kfs[kfs.size() / 2] >= 128.0;
         }
     }
-    const double L = M - 1;
-    t.fl_chain_obs = double(h.n_used) * p * p * L * L;
+    if (fa && M < int(t.prior_tasks.size())) {
+        const double nr = double(t.prior_tasks[M].size());
+        t.fl_chain[M] = nr * p * p * p * double(M - 1) * (M - 1);
+        t.fl_pfin[M] = nr * p * p * p * (double(M - 1) + 2.0 / 3.0);
+    }
+    const double L = M - 1, Lc = fa ? M : M - 1, Ls = fa ? 1 : M - 1;
+    t.fl_chain_obs = double(h.n_used) * p * p * Lc * Lc;
     auto fl = [&](int g) {
         const double n = double(h.obs_hi[g] - h.obs_lo[g]);
-        return L * n * n * p + n * n * n / 3.0 + n * n * (L * p + 1);
+        return Ls * n * n * p + n * n * n / 3.0 + n * n * (L * p + 1);
     };
     auto fls = [&](int g) {
         const double n = double(h.obs_hi[g] - h.obs_lo[g]);
-        return L * n * n * p;
+        return Ls * n * n * p;
     };
     t.fl_leaf = t.fl_leaf_s = 0.0;
     for (int g : t.leaf_tasks) t.fl_leaf += fl(g), t.fl_leaf_s += fls(g);
@@ -259,10 +267,11 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
                      const PlanOpts* opts, Plan& t, std::string& err) {
     const int64_t smax = opts ? opts->small_max : 64;
     const int M = h.M, P = h.P;
+    const bool fa = (flags & MRA_FURTHER_APPROX) != 0;
     t.form.assign(h.nreg, FOLD_FACTOR);
     t.vst_off.assign(h.nreg, -1);
     t.gram_off.assign(h.nreg, -1);
-    t.prior_tasks.assign(M, {});
+    t.prior_tasks.assign(M + 1, {});
     t.factor_tasks.assign(M, {});
     t.gram_tasks.assign(M, {});
     for (int q = 0; q < 3; ++q) t.fsmall_tasks[q].assign(M, {});
@@ -316,9 +325,20 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
                 ++t.n_gram;
             }
         }
-        if (m == M - 1)
+        if (m == M - 1 && !fa)
             for (int g : t.prior_tasks[m])
                 if (h.obs_hi[g] > h.obs_lo[g]) t.chain_obs_tasks.push_back(g);
+    }
+    if (fa) {
+        // the leaves' own knots: a prior (M blocks of V store each) for every
+        // leaf with observations, and the observation rows tasked per leaf
+        for (int64_t g = h.lvl_start[M - 1]; g < h.lvl_start[M]; ++g) {
+            if (h.obs_hi[g] == h.obs_lo[g]) continue;
+            t.prior_tasks[M].push_back(int(g));
+            t.vst_off[g] = vo;
+            vo += int64_t(M) * P * P;
+            t.chain_obs_tasks.push_back(int(g));
+        }
     }
     t.vst_size = std::max<int64_t>(vo, 1);
     t.gram_size = std::max<int64_t>(go, 1);
@@ -341,7 +361,7 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
     }
     t.s0_size = std::max<int64_t>((s0 + 31) & ~int64_t(31), 1);
     t.root_gram = (M > 1 && t.form[0] == FOLD_GRAM && t.gram_off[0] >= 0) ? 1 : 0;
-    plan_flops(h, t);
+    plan_flops(h, t, fa);
     if (opts)
         for (int m = 1; m < M && m < int(opts->tile.size()); ++m)
             if (opts->tile[m] >= 0) t.gtile_super[m] = opts->tile[m];
@@ -354,10 +374,14 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
         err = "device allocation failed for the execution plan";
         return rc;
     }
-    t.d_prior.assign(M, nullptr);
+    t.d_prior.assign(M + 1, nullptr);
     t.d_factor.assign(M, nullptr);
     t.d_gramt.assign(M, nullptr);
     for (int q = 0; q < 3; ++q) t.d_fsmall[q].assign(M, nullptr);
+    if (fa && (rc = upload(&t.d_prior[M], t.prior_tasks[M]))) {
+        err = "device allocation failed for the execution plan";
+        return rc;
+    }
     for (int m = 1; m < M; ++m)
         if ((rc = upload(&t.d_prior[m], t.prior_tasks[m])) || (rc = upload(&t.d_factor[m], t.factor_tasks[m])) ||
             (rc = upload(&t.d_gramt[m], t.gram_tasks[m])) || (rc = upload(&t.d_fsmall[0][m], t.fsmall_tasks[0][m])) ||
@@ -539,13 +563,14 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
     }
     if (rc) { delete t; return fail(rc, err); }
     const HostTree& h = t->h;
-    if (M - 1 > chain_lmax(h.P)) {
+    if (M - 1 + ((flags & MRA_FURTHER_APPROX) ? 1 : 0) > chain_lmax(h.P)) {
         delete t;
         return fail(MRA_EINVAL, "M - 1 = " + std::to_string(M - 1) + " exceeds " + std::to_string(chain_lmax(h.P)) +
                                     " levels above the finest");
     }
     t->WF = (M - 1) * h.P + 1;
-    t->WFs = (t->WF + 3) & ~3;
+    t->fa_cols = (flags & MRA_FURTHER_APPROX) ? h.P : 0;
+    t->WFs = (t->fa_cols + t->WF + 3) & ~3;
     t->leaf_min = INT64_MAX;
     for (int64_t g = h.lvl_start[M - 1]; g < h.lvl_start[M]; ++g) {
         const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
@@ -658,6 +683,7 @@ static KArgs base_args(const mra_tree* t, const Plan& pl, int smooth) {
     a.d_stride = h.nreg;
     a.n_used = double(h.n_used);
     a.zero_nugget = (t->flags & MRA_ALLOW_ZERO_NUGGET) ? 1 : 0;
+    a.fa = t->fa_cols > 0 ? 1 : 0;
     a.rep = nullptr;
     a.leaf_phase = -1;
     a.S0 = nullptr;
@@ -672,7 +698,8 @@ static hipError_t enqueue_prior(const mra_tree* t, const Plan& pl, KArgs a, int 
     if (nth < 0) nth = nb;
     const int M = t->h.M;
     hipError_t e;
-    for (int m = 1; m < M; ++m) {
+    const int Mk = a.fa ? M : M - 1;  // levels with knots
+    for (int m = 1; m <= Mk; ++m) {
         a.level = m;
         a.tasks = pl.d_prior[m];
         a.ntasks = int64_t(pl.prior_tasks[m].size());
@@ -681,8 +708,8 @@ static hipError_t enqueue_prior(const mra_tree* t, const Plan& pl, KArgs a, int 
         if (m > 1 && (e = timed(0, m, pl.fl_chain[m] * nth, st, [&] { return launch_chain(a, 0, grid, st); }))) return e;
         if ((e = timed(1, m, pl.fl_pfin[m] * nth, st, [&] { return launch_prior_finish(a, grid, st); }))) return e;
     }
-    if (M > 1 && !pl.chain_obs_tasks.empty()) {
-        a.level = M - 1;
+    if (Mk >= 1 && !pl.chain_obs_tasks.empty()) {
+        a.level = M - 1 + a.fa;
         a.tasks = pl.d_chain_obs;
         a.ntasks = int64_t(pl.chain_obs_tasks.size());
         const int grid = int(std::min<int64_t>(a.ntasks * nb, 1 << 16));
@@ -992,7 +1019,7 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
     }
     std::vector<int> hstatus;
     KArgs a = base_args(t, t->lik, smooth);
-    a.vst = w.vst; a.F = w.F; a.gram = w.gram; a.dval = w.dval;
+    a.vst = w.vst; a.F = w.F + t->fa_cols; a.gram = w.gram; a.dval = w.dval;
     a.scratch = w.scratch; a.scratch_stride = w.scratch_per;
     bool profiling;
     {
@@ -1143,7 +1170,7 @@ extern "C" int mra_loglik_noalloc(const mra_tree* t, int family, double nu, cons
     int* status = reinterpret_cast<int*>(base);
     double* p = base + st_sz;
     a.vst = p; p += Bc * al32(pl.vst_size);
-    a.F = p; p += Bc * al32(F_stride);
+    a.F = p + t->fa_cols; p += Bc * al32(F_stride);
     a.gram = p; p += Bc * al32(pl.gram_size);
     a.dval = p; p += Bc * al32(h.nreg);
     a.scratch = p;
@@ -1323,6 +1350,7 @@ extern "C" int mra_predict(const mra_tree* t, int family, double nu, const doubl
     int smooth = 0;
     int rc = smooth_of(family, nu, &smooth);
     if (rc) return rc;
+    if (t->fa_cols) return fail(MRA_EINVAL, "kriging is not provided for a tree built with MRA_FURTHER_APPROX");
     if (np == 0) return MRA_OK;
     const HostTree& h = t->h;
     const int M = h.M;

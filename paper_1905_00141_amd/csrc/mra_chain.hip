@@ -73,8 +73,11 @@ __global__ void __launch_bounds__(NT, 2) k_chain(KArgs a) {
     __shared__ int sld[MAXL * (MAXL + 1) / 2];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, lr = lane & 15, lg = lane >> 4;
     const int64_t total = a.ntasks * a.ntheta;
-    const int m = mode == 0 ? a.level : a.M - 1;  // level of the task region
-    const int L = mode == 0 ? m - 1 : a.M - 1;    // ancestor levels of the rows
+    // level of the task region and ancestor levels of the rows; observation
+    // rows of the further approximation are tasked per leaf and include the
+    // leaf's own knots (its level-M block lands at column -P)
+    const int m = mode == 0 ? a.level : a.M - 1 + a.fa;
+    const int L = mode == 0 ? m - 1 : a.M - 1 + a.fa;
     int ph = 0;  // staging buffer parity, continued across tiles and tasks
     for (int q = threadIdx.x; q < P; q += NT) kq[q] = q < a.rhat ? (q % a.nx) + 8 * (q / a.nx) : -1;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {

@@ -110,8 +110,10 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 3 : 1)) k_small(KArgs a) {
     const int M = a.M, P = a.P;
     double* Tw = T[w];
     double* Tiw = T[w];
-    const int kc0 = MODE == FIN_LEAF ? 0 : (M - 1 - a.level) * P;  // first column of the product
-    const int K = MODE == FIN_LEAF ? (M - 1) * P : P;
+    // first column of the product and its width (the further approximation:
+    // the leaf's own-knot columns W before column 0, the matrix W W^T + tau I)
+    const int kc0 = MODE == FIN_LEAF ? (a.fa ? -P : 0) : (M - 1 - a.level) * P;
+    const int K = MODE == FIN_LEAF ? (a.fa ? P : (M - 1) * P) : P;
     const int tc0 = MODE == FIN_LEAF ? 0 : kc0 + P;                  // first column of the solve
     for (int64_t t = int64_t(blockIdx.x) * 4 + w; t < total; t += int64_t(gridDim.x) * 4) {
         const int th = int(t / a.ntasks);
@@ -175,14 +177,15 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 3 : 1)) k_small(KArgs a) {
                 for (int ct = 0; ct <= rt; ++ct) {
                     const int c = 16 * ct + lr;
                     double cx = 0.0, cy = 0.0;
-                    if (MODE == FIN_LEAF && c < n) { cx = a.x[lo + c]; cy = a.y[lo + c]; }
+                    if (MODE == FIN_LEAF && !a.fa && c < n) { cx = a.x[lo + c]; cy = a.y[lo + c]; }
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int r = 16 * rt + lg + 4 * i;
                         double v;
                         if (r < n && c < n) {
                             if (MODE == FIN_LEAF) {
-                                v = cov_pts(a.x[lo + r], a.y[lo + r], cx, cy, alpha, inv_beta, a.smooth) - acc[e][i];
+                                v = a.fa ? acc[e][i]
+                                         : cov_pts(a.x[lo + r], a.y[lo + r], cx, cy, alpha, inv_beta, a.smooth) - acc[e][i];
                                 if (r == c && !s0_build) v += tau;
                             } else {
                                 v = acc[e][i] + (r == c ? 1.0 : 0.0);
@@ -275,8 +278,10 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
     const int64_t total = a.ntasks * a.ntheta;
     const int M = a.M, P = a.P;
-    const int cm = MODE == FIN_LEAF ? 0 : (M - 1 - a.level) * P;  // first product column
-    const int K = MODE == FIN_LEAF ? (M - 1) * P : P;             // product columns
+    // first product column and product columns (the further approximation:
+    // the leaf's own-knot columns W before column 0, the matrix W W^T + tau I)
+    const int cm = MODE == FIN_LEAF ? (a.fa ? -P : 0) : (M - 1 - a.level) * P;
+    const int K = MODE == FIN_LEAF ? (a.fa ? P : (M - 1) * P) : P;
     const int xc0 = MODE == FIN_LEAF ? 0 : cm + P;                 // first right-hand-side column
     const int W = a.WF - xc0;                                      // right-hand-side columns
     const int nsl = (W + 15) / 16;                                 // 16-column slices
@@ -353,14 +358,14 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
                     const int cc = 16 * (cg + c) + lr;
                     if (cg + c > st || cc >= n) continue;
                     double cx = 0.0, cy = 0.0;
-                    if (MODE == FIN_LEAF) { cx = px[cc]; cy = py[cc]; }
+                    if (MODE == FIN_LEAF && !a.fa) { cx = px[cc]; cy = py[cc]; }
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const int rr = 16 * st + lg + 4 * i;
                         if (rr < n && cc <= rr) {
                             double v;
                             if (MODE == FIN_LEAF) {
-                                v = cov_pts(px[rr], py[rr], cx, cy, alpha, inv_beta, a.smooth) - acc[c][i];
+                                v = a.fa ? acc[c][i] : cov_pts(px[rr], py[rr], cx, cy, alpha, inv_beta, a.smooth) - acc[c][i];
                                 if (rr == cc && !s0_build) v += tau;
                             } else {
                                 v = acc[c][i] + (rr == cc ? 1.0 : 0.0);

@@ -70,6 +70,12 @@ struct KArgs {
     double* out_lev;          // final (optional): per theta, M sums of log-determinants, one per level
     double n_used;
     int zero_nugget;          // 1: tau = 0 is a valid nugget
+    // 1: knots at the finest level too (the further approximation): the
+    // observation rows carry one more level, the leaf's own knots, in the P
+    // columns before column 0 of a row (rows are WFs apart, F points P
+    // columns into the first row), and the finest-level matrix is W W^T +
+    // tau I with W those columns
+    int fa;
     // prediction (one theta): points grouped by leaf
     const double* px;
     const double* py;

@@ -20,6 +20,7 @@ MRA_EXP, MRA_MATERN, MRA_GAUSS = 0, 1, 2
 MRA_DEVICE_PTRS = 1 << 0
 MRA_ELIM_DUPLICATES = 1 << 1
 MRA_ALLOW_ZERO_NUGGET = 1 << 2
+MRA_FURTHER_APPROX = 1 << 3  # r knots at the finest level too (the further approximation; no kriging)
 MRA_FOLD_GRAM = 1 << 4
 MRA_FOLD_FACTOR = 1 << 5
 
