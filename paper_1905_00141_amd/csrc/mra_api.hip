@@ -359,6 +359,15 @@ static int make_plan(const HostTree& h, uint32_t flags, bool gram_only, const st
             t.small_tasks[0].push_back(int(g));
         }
     }
+    // the workgroup finishers take their tasks largest first (longest
+    // processing time first: the last tasks to start are the short ones)
+    auto by_size = [&h](std::vector<int>& v) {
+        std::stable_sort(v.begin(), v.end(), [&h](int p, int q) {
+            return h.obs_hi[p] - h.obs_lo[p] > h.obs_hi[q] - h.obs_lo[q];
+        });
+    };
+    by_size(t.leaf_tasks);
+    for (int m = 1; m < M; ++m) by_size(t.factor_tasks[m]);
     t.s0_size = std::max<int64_t>((s0 + 31) & ~int64_t(31), 1);
     t.root_gram = (M > 1 && t.form[0] == FOLD_GRAM && t.gram_off[0] >= 0) ? 1 : 0;
     plan_flops(h, t, fa);
@@ -653,6 +662,10 @@ static int region_level(const HostTree& h, int64_t g) {
 // (status: per theta 0 or 1 + the global index of the failing region).
 static int status_message(const HostTree& h, const int* status, int64_t B) {
     for (int64_t b = 0; b < B; ++b)
+        if (status[b] < 0)
+            return fail(MRA_EDEVICE, "theta " + std::to_string(b) +
+                                         ": a finisher's bounded wait for the theta sharing its prior ran out");
+    for (int64_t b = 0; b < B; ++b)
         if (status[b] != 0) {
             const int64_t g = status[b] - 1;
             const int lev = region_level(h, g);
@@ -686,6 +699,8 @@ static KArgs base_args(const mra_tree* t, const Plan& pl, int smooth) {
     a.fa = t->fa_cols > 0 ? 1 : 0;
     a.rep = nullptr;
     a.leaf_phase = -1;
+    a.order = a.need = nullptr;
+    a.wait = a.queue = nullptr;
     a.S0 = nullptr;
     a.S0_off = pl.d_s0_off;
     a.S0_stride = pl.s0_size;
@@ -720,25 +735,34 @@ static hipError_t enqueue_prior(const mra_tree* t, const Plan& pl, KArgs a, int 
 
 // Finest-level factors of the observations for one chunk.
 // nth: theta whose tasks run in this launch sequence (the flop count).
+// leaf_phase 3: the one-wave finishers run phase 0 and then phase 1, the
+// workgroup finisher runs every theta in one launch (see KArgs::wait).
 static hipError_t enqueue_leaves(const mra_tree* t, const Plan& pl, KArgs a, int nb, int64_t nslot, hipStream_t st,
-                                 double nth = -1) {
+                                 double nth = -1, double nrep = 0) {
     if (nth < 0) nth = nb;
     const int M = t->h.M;
     hipError_t e;
     a.level = M;
+    const int phase = a.leaf_phase;
     for (int q = 0; q < 3; ++q) {
         a.tasks = pl.d_small[q];
         a.ntasks = int64_t(pl.small_tasks[q].size());
-        const double fq = a.leaf_phase == 2 ? pl.fl_small_s[q] : a.leaf_phase >= 0 ? pl.fl_small[q] - pl.fl_small_s[q]
-                                                                                    : pl.fl_small[q];
-        if (a.ntasks > 0 && (e = timed(6, M, fq * nth, st, [&] {
-                                 return launch_small(a, 16 << q, 0, int(std::min<int64_t>(a.ntasks * nb, 1 << 18)), st);
-                             })))
-            return e;
+        const double fq = phase == 2 ? pl.fl_small_s[q] : phase >= 0 ? pl.fl_small[q] - pl.fl_small_s[q]
+                                                                     : pl.fl_small[q];
+        for (int ph : phase == 3 ? std::initializer_list<int>{0, 1} : std::initializer_list<int>{phase}) {
+            a.leaf_phase = ph;
+            const double nq = phase != 3 ? nth : ph == 0 ? nb - nrep : nrep;
+            if (a.ntasks > 0 && (e = timed(6, M, fq * nq, st, [&] {
+                                     return launch_small(a, 16 << q, 0, int(std::min<int64_t>(a.ntasks * nb, 1 << 18)), st);
+                                 })))
+                return e;
+        }
+        a.leaf_phase = phase;
     }
     a.tasks = pl.d_leaf;
     a.ntasks = int64_t(pl.leaf_tasks.size());
     const double fl = a.leaf_phase == 2 ? pl.fl_leaf_s : a.leaf_phase >= 0 ? pl.fl_leaf - pl.fl_leaf_s : pl.fl_leaf;
+    if (phase == 3 && a.ntasks > 0 && (e = launch_fill_int(a.wait, a.ntasks * nb, 0, st))) return e;
     if (a.ntasks > 0 && (e = timed(2, M, fl * nth, st, [&] {
                              return launch_leaf(a, int(std::min<int64_t>(a.ntasks * nb, nslot)), st);
                          })))
@@ -797,7 +821,9 @@ struct Workspace {
     double *vst = nullptr, *F = nullptr, *gram = nullptr, *dval = nullptr, *scratch = nullptr;
     double *th = nullptr, *out = nullptr, *ld = nullptr, *q = nullptr;
     int* status = nullptr;
-    int* rep = nullptr;  // per theta of a chunk: its representative (shared prior)
+    int* rep = nullptr;  // per theta of a chunk: its representative, the finisher's order, group sizes
+    int* wait = nullptr;   // per leaf task and theta of a chunk: the group's count (merged leaf launch)
+    int* queue = nullptr;  // the finishers' work-queue counters
     double* S0 = nullptr;  // per theta of a chunk: C - V V^T of every leaf (shared prior)
     int64_t Bc = 0, nslot = 0, scratch_per = 0, cap_B = 0;
     bool mem_limited = false;  // Bc was capped by device memory, not by the request
@@ -818,10 +844,11 @@ struct Workspace {
         for (void* p : {static_cast<void*>(vst), static_cast<void*>(F), static_cast<void*>(gram),
                         static_cast<void*>(dval), static_cast<void*>(scratch), static_cast<void*>(th),
                         static_cast<void*>(out), static_cast<void*>(ld), static_cast<void*>(q),
-                        static_cast<void*>(status), static_cast<void*>(rep), static_cast<void*>(S0)})
+                        static_cast<void*>(status), static_cast<void*>(rep), static_cast<void*>(S0),
+                        static_cast<void*>(wait), static_cast<void*>(queue)})
             if (p) (void)hipFree(p);
         vst = F = gram = dval = scratch = th = out = ld = q = S0 = nullptr;
-        status = rep = nullptr;
+        status = rep = wait = queue = nullptr;
         Bc = nslot = cap_B = 0;
         used = false;
     }
@@ -872,7 +899,9 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
         !al(reinterpret_cast<void**>(&w.dval), size_t(Bc) * h.nreg * 8) ||
         !al(reinterpret_cast<void**>(&w.scratch), size_t(nslot) * scratch_per * 8) ||
         !al(reinterpret_cast<void**>(&w.status), size_t(capB) * sizeof(int)) ||
-        !al(reinterpret_cast<void**>(&w.rep), size_t(capB) * sizeof(int)) ||
+        !al(reinterpret_cast<void**>(&w.rep), size_t(capB) * 3 * sizeof(int)) ||
+        !al(reinterpret_cast<void**>(&w.wait), size_t(Bc) * pl.leaf_tasks.size() * sizeof(int)) ||
+        !al(reinterpret_cast<void**>(&w.queue), 2 * sizeof(int)) ||
         !al(reinterpret_cast<void**>(&w.S0), size_t(Bc) * pl.s0_size * 8) ||
         !al(reinterpret_cast<void**>(&w.th), size_t(capB) * 3 * 8) ||
         !al(reinterpret_cast<void**>(&w.out), size_t(capB) * 8) ||
@@ -915,6 +944,7 @@ static hipError_t enqueue_loglik(const mra_tree* t, int64_t Bc, int64_t nslot, K
         prof = g_prof_on;
     }
     if ((e = launch_fill_int(status, B, 0, st))) return e;
+    if (a.queue && (e = launch_fill_int(a.queue, 2, 0, st))) return e;
     for (int64_t b0 = 0; b0 < B; b0 += Bc) {
         const int nb = int(std::min<int64_t>(Bc, B - b0));
         a.theta = d_th + 3 * b0;
@@ -951,11 +981,21 @@ static hipError_t enqueue_loglik(const mra_tree* t, int64_t Bc, int64_t nslot, K
             a.S0 = s0_buf;
             a.leaf_phase = 2;  // C - V V^T of every leaf, once per representative
             if ((e = enqueue_leaves(t, pl, a, nb, nslot, st, nrep))) return e;
-            a.leaf_phase = 0;  // the theta that share a prior, from their representative's rows
-            if ((e = enqueue_leaves(t, pl, a, nb, nslot, st, nb - nrep))) return e;
-            a.leaf_phase = 1;  // then the representatives, in place
-            if ((e = enqueue_leaves(t, pl, a, nb, nslot, st, nrep))) return e;
-            a.rep = nullptr;
+            // the theta that share a prior from their representative's rows,
+            // then the representatives in place (the workgroup finisher: in
+            // one launch, which needs the work queue)
+            if (a.queue && a.wait) {
+                a.leaf_phase = 3;
+                a.order = rep_buf + nb;
+                a.need = rep_buf + 2 * nb;
+                if ((e = enqueue_leaves(t, pl, a, nb, nslot, st, nb, nrep))) return e;
+            } else {
+                a.leaf_phase = 0;
+                if ((e = enqueue_leaves(t, pl, a, nb, nslot, st, nb - nrep))) return e;
+                a.leaf_phase = 1;
+                if ((e = enqueue_leaves(t, pl, a, nb, nslot, st, nrep))) return e;
+            }
+            a.rep = a.order = a.need = nullptr;
             a.S0 = nullptr;
             a.leaf_phase = -1;
         } else if ((e = enqueue_leaves(t, pl, a, nb, nslot, st))) {
@@ -1021,6 +1061,7 @@ static int loglik_impl(const mra_tree* t, int family, double nu, const double* t
     KArgs a = base_args(t, t->lik, smooth);
     a.vst = w.vst; a.F = w.F + t->fa_cols; a.gram = w.gram; a.dval = w.dval;
     a.scratch = w.scratch; a.scratch_stride = w.scratch_per;
+    a.queue = w.queue; a.wait = w.wait;
     bool profiling;
     {
         std::lock_guard<std::mutex> pk(g_prof_mu);
@@ -1150,12 +1191,12 @@ extern "C" int mra_loglik_noalloc(const mra_tree* t, int family, double nu, cons
     if ((rc = noalloc_base(dev, &base))) return rc;
     const HostTree& h = t->h;
     const Plan& pl = t->lik;
-    // layout (doubles, each part 256-byte aligned): status (B ints), then
-    // Bc theta of V stores, F rows, Gram blocks and log-determinants, then
-    // nslot workgroup slots
+    // layout (doubles, each part 256-byte aligned): status (B ints) and the
+    // finishers' queue counters, then Bc theta of V stores, F rows, Gram
+    // blocks and log-determinants, then nslot workgroup slots
     auto al32 = [](int64_t v) { return (v + 31) & ~int64_t(31); };
     const int64_t cap = int64_t(NOALLOC_BYTES / sizeof(double));
-    const int64_t st_sz = al32((B * int64_t(sizeof(int)) + 7) / 8);
+    const int64_t st_sz = al32((B * int64_t(sizeof(int)) + 7) / 8) + 32;
     const int64_t F_stride = std::max<int64_t>(h.n_used, 1) * t->WFs;
     const int64_t per_theta = al32(pl.vst_size) + al32(F_stride) + al32(pl.gram_size) + al32(h.nreg);
     const int64_t slot = al32(std::max<int64_t>({pl.scratch_leaf, pl.scratch_fold, 1}));
@@ -1168,6 +1209,7 @@ extern "C" int mra_loglik_noalloc(const mra_tree* t, int family, double nu, cons
     const int64_t Bc = std::min<int64_t>(B, (cap - st_sz - nslot * slot) / per_theta);
     KArgs a = base_args(t, pl, smooth);
     int* status = reinterpret_cast<int*>(base);
+    a.queue = reinterpret_cast<int*>(base + st_sz - 32);  // zeroed at the start of the launch sequence
     double* p = base + st_sz;
     a.vst = p; p += Bc * al32(pl.vst_size);
     a.F = p + t->fa_cols; p += Bc * al32(F_stride);

@@ -99,6 +99,34 @@ __device__ __forceinline__ void flag_fail(const KArgs& a, int th, int64_t g) {
     if (threadIdx.x == 0) atomicCAS(a.status + th, 0, int(g + 1));
 }
 
+// ------------------------------------------------ finisher work queue
+
+// The workgroup's next task: with a queue, the next ticket (every thread gets
+// the same value; *tick is one int of LDS), else grid-stride from blockIdx.x.
+// The barrier before the ticket keeps a fast thread from overwriting *tick
+// while a slow one still reads the previous value.
+__device__ __forceinline__ int64_t next_task(const KArgs& a, int64_t t, int* tick) {
+    if (!a.queue) return t < 0 ? int64_t(blockIdx.x) : t + gridDim.x;
+    __syncthreads();
+    if (threadIdx.x == 0) *tick = __hip_atomic_fetch_add(a.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*tick);
+}
+
+// End of a queued launch: the last workgroup to finish sets both counters
+// back to zero for the next launch on the stream.
+__device__ __forceinline__ void queue_done(const KArgs& a) {
+    if (!a.queue || threadIdx.x != 0) return;
+    if (__hip_atomic_fetch_add(a.queue + 1, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == int(gridDim.x) - 1) {
+        __hip_atomic_store(a.queue, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.queue + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Status of a theta whose representative's task gave up waiting (a bounded
+// wait; not expected to happen, see the leaf finisher).
+constexpr int STATUS_WAIT = -1;
+
 // ---------------------------------------------------- workgroup primitives
 
 enum { MM_ADD = 0, MM_SUB = 1, MM_SET = 2 };

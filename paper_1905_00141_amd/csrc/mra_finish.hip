@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(NT, (NMAX <= 32 ? 3 : 1)) k_small(KArgs a) {
 constexpr int FPD = 66;  // LDS pitch of the 64-column tiles (matrix-core operand reads hit each bank twice)
 
 template <int MODE>
-__device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn, double* red, int* flag) {
+__device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn, double* red, int* flag, int* tick) {
     const int tid = threadIdx.x, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform
     const int64_t total = a.ntasks * a.ntheta;
@@ -286,10 +286,16 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
     const int W = a.WF - xc0;                                      // right-hand-side columns
     const int nsl = (W + 15) / 16;                                 // 16-column slices
     double* Ag = a.scratch + int64_t(blockIdx.x) * a.scratch_stride;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const int th = int(t / a.ntasks);
-        if (MODE == FIN_LEAF && a.rep && (a.leaf_phase == 0) == (a.rep[th] == th)) continue;  // uniform
-        const int64_t g = a.tasks[t % a.ntasks];
+    // tasks theta-minor: all theta of the first region, then of the next
+    // (regions come largest first, so that the longest tasks start first)
+    const bool merged = MODE == FIN_LEAF && a.rep && a.leaf_phase == 3;
+    for (int64_t t = next_task(a, -1, tick); t < total; t = next_task(a, t, tick)) {
+        const int64_t ti = t / a.ntheta;
+        const int p = int(t - ti * a.ntheta);
+        const int th = merged ? __builtin_amdgcn_readfirstlane(a.order[p]) : p;
+        const bool is_rep = MODE == FIN_LEAF && a.rep && a.rep[th] == th;
+        if (MODE == FIN_LEAF && a.rep && !merged && (a.leaf_phase == 0) == is_rep) continue;  // uniform
+        const int64_t g = a.tasks[ti];
         const int64_t lo = a.obs_lo[g];
         const int n = int(a.obs_hi[g] - lo);
         const int lda = (n + 3) & ~3;
@@ -299,7 +305,7 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
         // rows read at their first touch (the matrix, and every row in the
         // first block step): [V | z] of the representative for a theta that
         // shares it, else the theta's own
-        const double* Fs = (MODE == FIN_LEAF && a.rep && a.leaf_phase == 0) ? a.F + a.rep[th] * a.F_stride + lo * a.WFs : Fr;
+        const double* Fs = (MODE == FIN_LEAF && a.rep && !is_rep) ? a.F + a.rep[th] * a.F_stride + lo * a.WFs : Fr;
         const double* px = a.x + lo;
         const double* py = a.y + lo;
         // a shared prior: C - V V^T of the leaf, formed once per representative
@@ -307,8 +313,23 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
         const bool s0_build = MODE == FIN_LEAF && a.S0 && a.leaf_phase == 2;
         const bool s0_use = MODE == FIN_LEAF && a.S0 && a.leaf_phase != 2;
         double* S0p = (MODE == FIN_LEAF && a.S0) ? a.S0 + a.rep[th] * a.S0_stride + a.S0_off[g - a.lvl[M - 1]] : nullptr;
-        if (MODE == FIN_LEAF && !s0_build)
+        // (a representative's own rows already hold z: its chain wrote them)
+        if (MODE == FIN_LEAF && !s0_build && !(merged && is_rep))
             for (int r = tid; r < n; r += NT) Fr[int64_t(r) * a.WFs + (a.WF - 1)] = a.z[lo + r];
+        // one launch for the whole group: a theta reading its representative's
+        // rows counts itself done once past the first block step (or on
+        // failure); the representative's task, taken from the queue after
+        // all of them (so each is running or finished), waits for that count
+        // before it writes its rows
+        bool released = !(merged && !is_rep);
+        auto release = [&]() {
+            if (released) return;
+            released = true;
+            __syncthreads();  // every read of the representative's rows is done
+            if (tid == 0)
+                __hip_atomic_fetch_add(a.wait + ti * a.ntheta + a.rep[th], 1, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        };
         // ---- 1. the matrix: 16-row strips (round robin over the waves),
         // 64 columns (four 16 x 16 tiles) at a time, lower triangle
         double* Sd = s0_build ? S0p : Ag;
@@ -375,6 +396,21 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
                     }
                 }
             }
+        }
+        if (merged && is_rep) {
+            if (tid == 0) {
+                const int need = a.need[th];
+                const int* c = a.wait + ti * a.ntheta + th;
+                int it = 0;
+                while (__hip_atomic_load(c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need && ++it < (1 << 22))
+                    __builtin_amdgcn_s_sleep(8);
+                *flag = it >= (1 << 22) ? 1 : 0;
+                if (*flag)  // (bounded wait ran out) the group's results are void
+                    for (int i = 0; i < a.ntheta; ++i)
+                        if (a.rep[i] == th) atomicCAS(a.status + i, 0, STATUS_WAIT);
+            }
+            __syncthreads();
+            if (*flag) continue;  // uniform
         }
         __syncthreads();
         if (s0_build) continue;  // uniform: phase 2 forms the matrix only
@@ -607,7 +643,9 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
                 }
                 __syncthreads();
             }
+            if (j0 == 0) release();
         }
+        release();  // (a failed first block step)
         if (failed) {
             flag_fail(a, th, g);
             __syncthreads();
@@ -616,22 +654,23 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
         if (tid == 0) a.dval[th * a.d_stride + g] = 2.0 * logdet;
         __syncthreads();
     }
+    queue_done(a);
 }
 
 __global__ void __launch_bounds__(NT, 2) k_leaf_finish(KArgs a) {
     __shared__ double Tt[64 * FPD];
     __shared__ double Pn[64 * FPD];
     __shared__ double red[4];
-    __shared__ int flag;
-    fin_body<FIN_LEAF>(a, Tt, Pn, red, &flag);
+    __shared__ int flag, tick;
+    fin_body<FIN_LEAF>(a, Tt, Pn, red, &flag, &tick);
 }
 
 __global__ void __launch_bounds__(NT, 2) k_fold_factor(KArgs a) {
     __shared__ double Tt[64 * FPD];
     __shared__ double Pn[64 * FPD];
     __shared__ double red[4];
-    __shared__ int flag;
-    fin_body<FIN_FOLD>(a, Tt, Pn, red, &flag);
+    __shared__ int flag, tick;
+    fin_body<FIN_FOLD>(a, Tt, Pn, red, &flag, &tick);
 }
 
 // ---- host-side launchers

@@ -521,7 +521,10 @@ __global__ void k_fill_int(int* p, int64_t n, int v) {
 }
 
 // Representatives of a chunk's theta: rep[i] = the first j <= i with the same
-// alpha and range (the prior does not involve the nugget).
+// alpha and range (the prior does not involve the nugget).  Also, in
+// rep[nb ..], the theta in the order the leaf finisher takes them (the others
+// first, then the representatives) and in rep[2 nb ..], per representative,
+// the number of other theta in its group.  One workgroup.
 __global__ void k_rep(const double* theta, int nb, int* rep) {
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {
         int r = i;
@@ -531,6 +534,20 @@ __global__ void k_rep(const double* theta, int nb, int* rep) {
                 break;
             }
         rep[i] = r;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        int c = 0;
+        if (rep[i] == i)
+            for (int j = i + 1; j < nb; ++j) c += rep[j] == i ? 1 : 0;
+        rep[2 * nb + i] = c;
+    }
+    if (threadIdx.x == 0) {
+        int k = 0;
+        for (int i = 0; i < nb; ++i)
+            if (rep[i] != i) rep[nb + k++] = i;
+        for (int i = 0; i < nb; ++i)
+            if (rep[i] == i) rep[nb + k++] = i;
     }
 }
 

@@ -55,6 +55,19 @@ struct KArgs {
     // representative's rows; 1 = the representatives, in place.
     const int* rep;
     int leaf_phase;
+    // leaf_phase 3 (the leaf finisher only): every theta in one launch.  A
+    // representative's task waits until the other theta of its group have
+    // read its rows: wait[task * ntheta + rep] counts them up to need[rep]
+    // (the group's size less one; the representative sets it back to zero).
+    // order lists the chunk's theta with the representatives last, so that a
+    // representative's task is taken from the queue after the others'.
+    const int* order;
+    const int* need;
+    int* wait;
+    // work queue of the finishers (null: grid-stride): a ticket counter and
+    // a count of finished workgroups, zero at launch and set back to zero by
+    // the last workgroup; tasks are taken in ticket order
+    int* queue;
     // leaf_phase 2 (representatives): C(S, S) - V V^T of every leaf (lower,
     // pitch n rounded up to 4) into S0 at the representative's slot; phases 0
     // and 1 then start from it (plus the nugget) instead of forming it
