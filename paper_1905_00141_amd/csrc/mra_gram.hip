@@ -83,12 +83,15 @@ __global__ void __launch_bounds__(NT, 2) k_gram_panel(KArgs a) {
                 const int nc = int(hi - lo);
                 if (nc == 0) continue;
                 const double* Fc = Fth + lo * a.WFs + cm;
+                // rows 0 .. D-2 of the block column on the matrix cores, the
+                // whole data row (D - 1) with the vector units
+                double* grow = G + int64_t(D - 1) * D;
                 if (first) {
-                    wg_mm<MM_SET>(G, D, D, P, nc, Fc, 1, a.WFs, Fc, 1, a.WFs, false, s.mm);
-                    wg_rowvec<false>(yrow, Dt, nc, Fc + (D - 1), a.WFs, Fc + P, a.WFs, s.mm);
+                    wg_mm<MM_SET>(G, D, D - 1, P, nc, Fc, 1, a.WFs, Fc, 1, a.WFs, false, s.mm);
+                    wg_rowvec<false>(grow, D, nc, Fc + (D - 1), a.WFs, Fc, a.WFs, s.mm);
                 } else {
-                    wg_mm<MM_ADD>(G, D, D, P, nc, Fc, 1, a.WFs, Fc, 1, a.WFs, false, s.mm);
-                    wg_rowvec<true>(yrow, Dt, nc, Fc + (D - 1), a.WFs, Fc + P, a.WFs, s.mm);
+                    wg_mm<MM_ADD>(G, D, D - 1, P, nc, Fc, 1, a.WFs, Fc, 1, a.WFs, false, s.mm);
+                    wg_rowvec<true>(grow, D, nc, Fc + (D - 1), a.WFs, Fc, a.WFs, s.mm);
                 }
                 first = false;
             } else {
@@ -136,19 +139,52 @@ __global__ void __launch_bounds__(NT, 2) k_gram_panel(KArgs a) {
             const int i = e / P, j = e % P;
             G[int64_t(i) * D + j] = (j <= i) ? s.L[i * MLD + j] : 0.0;
         }
-        // Z = G[P:D, 0:P] L^{-T} in place
+        // Z = G[P:D, 0:P] L^{-T} in place: the data row (Z's last) by the
+        // last wave, one column per lane, before its share of the blocks of
+        // the other rows on the matrix cores
         double* Z = G + int64_t(P) * D;
-        wg_mm<MM_SET>(Z, D, Dt, P, P, Z, D, 1, s.L, MLD, 1, false, s.mm);
-        // last row of S: yrow[c] -= Z[Dt-1] . Z[c]; lanes over the P columns
-        // of Z (coalesced rows), one row c per wave step, butterfly sum
-        {
-            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-            const double zy = lane < P ? Z[int64_t(Dt - 1) * D + lane] : 0.0;
-            for (int c = w; c < Dt; c += NT / 64) {
-                double v = lane < P ? zy * Z[int64_t(c) * D + lane] : 0.0;
+        if ((threadIdx.x >> 6) == NT / 64 - 1) {
+            // the row is read once (one value per lane) and broadcast lane by lane
+            const int lane = threadIdx.x & 63;
+            double* zl = Z + int64_t(Dt - 1) * D;
+            const double zr = ldg0(zl, lane, lane < P);
+            const int zlo = __double2loint(zr), zhi = __double2hiint(zr);
+            double v = 0.0;
 #pragma unroll
-                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-                if (lane == 0) yrow[c] -= v;
+            for (int k = 0; k < 64; ++k) {
+                const double zk = __hiloint2double(__builtin_amdgcn_readlane(zhi, k), __builtin_amdgcn_readlane(zlo, k));
+                v = fma(zk, (k < P && lane < P) ? s.L[lane * MLD + k] : 0.0, v);
+            }
+            if (lane < P) zl[lane] = v;
+        }
+        wg_mm<MM_SET>(Z, D, Dt - 1, P, P, Z, D, 1, s.L, MLD, 1, false, s.mm);
+        // last row of S: yrow[c] -= Z[Dt-1] . Z[c].  A wave step takes 8 rows
+        // c, two per 16-lane group; each lane multiplies four consecutive k
+        // (a row is read as one contiguous 512-byte run) and the group sums
+        // its lanes by shuffles in a fixed order
+        {
+            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, rs = lane >> 4, kq = lane & 15;
+            const double* zl = Z + int64_t(Dt - 1) * D;
+            double zk[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) zk[i] = ldg0(zl, 4 * kq + i, 4 * kq + i < P);
+            for (int c0 = 8 * w; c0 < Dt; c0 += 32) {
+                double v[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int c = c0 + 4 * h + rs;
+                    double zc[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) zc[i] = ldg0(Z, int64_t(c) * D + 4 * kq + i, c < Dt && 4 * kq + i < P);
+                    v[h] = fma(zk[0], zc[0], zk[1] * zc[1]) + fma(zk[2], zc[2], zk[3] * zc[3]);
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                    for (int off = 8; off > 0; off >>= 1) v[h] += __shfl_xor(v[h], off);
+                    const int c = c0 + 4 * h + rs;
+                    if (kq == 0 && c < Dt) yrow[c] -= v[h];
+                }
             }
         }
         __syncthreads();
