@@ -616,7 +616,7 @@ __device__ __forceinline__ void wg_trsm_lln(const double* L, int64_t ldl, int n,
 // ------------------------------------------------------------------ kernels
 
 struct Smem {
-    double mm[NT];  // reduction scratch (wg_rowvec)
+    double mm[NT];  // reduction scratch
     double L[TB * MLD];
     double Li[TB * MLD];
     double kx[TB], ky[TB];

@@ -22,40 +22,98 @@ __device__ __forceinline__ bool child_is_rows(const KArgs& a, int m, int64_t gc)
     return m + 1 == a.M || a.form[gc] == FOLD_FACTOR;
 }
 
-// y[c] (=|+=) sum_k u(k) v(k, c) for c < N, u(k) = U[k su], v(k, c) = V[k sv + c].
-// Lanes take 64 consecutive columns; the four waves take interleaved slices
-// of 8 rows, each lane keeping 8 independent partial sums so that 16 loads
-// are in flight; the partials are combined in a fixed order (deterministic).
-// red: 4 x 64 doubles of LDS.
-template <bool ADD>
-__device__ __forceinline__ void wg_rowvec(double* y, int N, int K, const double* U, int64_t su, const double* V,
-                                          int64_t sv, double* red) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int c0 = 0; c0 < N; c0 += 64) {
-        const int c = c0 + lane;
-        const bool ok = c < N;
-        double p[8];
+// The first block column of the Gram sum over one run of observation rows,
+// with its data row: for the rows' F columns f_0 .. f_{D-1} (f_{D-1} = z),
+//   G[r][c] (=|+=) sum_k f_r(k) f_c(k)   for r < D - 1, c < P   (matrix cores)
+//   G[D-1][r] (=|+=) sum_k z(k) f_r(k)   for r < D - 1          (vector units)
+//   G[D-1][D-1] (=|+=) sum_k z(k)^2
+// Each wave takes 64-row blocks round robin and, while its matrix products
+// run, multiplies the A fragments it has loaded by z (four more loads per
+// 16 k), so the data row costs no pass of its own.  F(k, c) = F[k ld + c].
+// Ends with a workgroup barrier.
+template <int MODE>
+__device__ __forceinline__ void panel_gather(double* G, int D, int P, int K, const double* F, int64_t ld) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const int R = D - 1, nbr = (R + TB - 1) / TB;
+    const double* zc = F + (D - 1);
+    double* grow = G + int64_t(D - 1) * D;
+    for (int br = w; br < nbr; br += NT / 64) {
+        const int r0 = br * TB;
+        v4d acc[4][4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) p[u] = 0.0;
-        for (int k = 8 * w; k < K; k += 32) {
-            double uv[8], vv[8];
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const bool kok = k + u < K;
-                uv[u] = ldg0(U, int64_t(k + u) * su, kok);
-                vv[u] = ldg0(V, int64_t(k + u) * sv + c, kok && ok);
+            for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+        double yp[4] = {0.0, 0.0, 0.0, 0.0}, zz = 0.0;
+        bool rok[4], cok[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            rok[t] = r0 + 16 * t + lr < R;
+            cok[t] = 16 * t + lr < P;
+        }
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            double fa[4][4], fb[4][4], zv[4];  // [tile][k-step]
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = k0 + 4 * q + lg;
+                const bool kok = k < K;
+                const double* row = F + (kok ? int64_t(k) * ld : 0);
+                zv[q] = kok ? zc[row - F] : 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double va = row[rok[t] ? r0 + 16 * t + lr : 0];
+                    const double vb = row[cok[t] ? 16 * t + lr : 0];
+                    fa[t][q] = (rok[t] && kok) ? va : 0.0;
+                    fb[t][q] = (cok[t] && kok) ? vb : 0.0;
+                }
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) p[u] = fma(uv[u], vv[u], p[u]);
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = mfma(fa[i][q], fb[j][q], acc[i][j]);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) yp[t] = fma(zv[q], fa[t][q], yp[t]);
+                if (br == 0) zz = fma(zv[q], zv[q], zz);
+            }
         }
-        red[w * 64 + lane] = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
-        __syncthreads();
-        if (w == 0 && ok) {
-            const double v = (red[lane] + red[64 + lane]) + (red[128 + lane] + red[192 + lane]);
-            y[c] = ADD ? y[c] + v : v;
+        // the data row: sum over the four lane groups (k = 4q + lg)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            yp[t] += __shfl_xor(yp[t], 16);
+            yp[t] += __shfl_xor(yp[t], 32);
+            const int r = r0 + 16 * t + lr;
+            if (lg == 0 && r < R) grow[r] = MODE == MM_ADD ? grow[r] + yp[t] : yp[t];
         }
-        __syncthreads();
+        if (br == 0) {
+            zz += __shfl_xor(zz, 16);
+            zz += __shfl_xor(zz, 32);
+            if (lane == 0) grow[D - 1] = MODE == MM_ADD ? grow[D - 1] + zz : zz;
+        }
+        // the block: one 16-row strip at a time, reads of G batched before writes
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double cold[4][4];
+            if (MODE == MM_ADD) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = r0 + 16 * i + lg + 4 * e, c = 16 * j + lr;
+                        cold[j][e] = ldg0(G, int64_t(r) * D + c, r < R && c < P);
+                    }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = r0 + 16 * i + lg + 4 * e, c = 16 * j + lr;
+                    if (r < R && c < P) G[int64_t(r) * D + c] = MODE == MM_ADD ? cold[j][e] + acc[i][j][e] : acc[i][j][e];
+                }
+        }
     }
+    __syncthreads();
 }
 
 __global__ void __launch_bounds__(NT, 2) k_gram_panel(KArgs a) {
@@ -83,16 +141,8 @@ __global__ void __launch_bounds__(NT, 2) k_gram_panel(KArgs a) {
                 const int nc = int(hi - lo);
                 if (nc == 0) continue;
                 const double* Fc = Fth + lo * a.WFs + cm;
-                // rows 0 .. D-2 of the block column on the matrix cores, the
-                // whole data row (D - 1) with the vector units
-                double* grow = G + int64_t(D - 1) * D;
-                if (first) {
-                    wg_mm<MM_SET>(G, D, D - 1, P, nc, Fc, 1, a.WFs, Fc, 1, a.WFs, false, s.mm);
-                    wg_rowvec<false>(grow, D, nc, Fc + (D - 1), a.WFs, Fc, a.WFs, s.mm);
-                } else {
-                    wg_mm<MM_ADD>(G, D, D - 1, P, nc, Fc, 1, a.WFs, Fc, 1, a.WFs, false, s.mm);
-                    wg_rowvec<true>(grow, D, nc, Fc + (D - 1), a.WFs, Fc, a.WFs, s.mm);
-                }
+                if (first) panel_gather<MM_SET>(G, D, P, nc, Fc, a.WFs);
+                else panel_gather<MM_ADD>(G, D, P, nc, Fc, a.WFs);
                 first = false;
             } else {
                 ++j;
