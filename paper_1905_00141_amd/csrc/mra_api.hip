@@ -579,7 +579,7 @@ extern "C" int mra_build_tree(const double* x, const double* y, const double* z,
     }
     t->WF = (M - 1) * h.P + 1;
     t->fa_cols = (flags & MRA_FURTHER_APPROX) ? h.P : 0;
-    t->WFs = (t->fa_cols + t->WF + 3) & ~3;
+    t->WFs = (t->fa_cols + t->WF + 15) & ~15;  // rows of whole 128-byte lines
     t->leaf_min = INT64_MAX;
     for (int64_t g = h.lvl_start[M - 1]; g < h.lvl_start[M]; ++g) {
         const int64_t nc = h.obs_hi[g] - h.obs_lo[g];
