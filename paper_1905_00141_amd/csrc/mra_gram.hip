@@ -403,7 +403,10 @@ __global__ void __launch_bounds__(NT, 2) k_gram_tile2(KArgs a) {
         const double* Fth = a.F + th * a.F_stride;
         const int R0 = BI * SB, C0 = BJ * SB;
         const int r0 = R0 + 64 * wr, c0 = C0 + 64 * wc;  // this wave's quarter (within S)
-        const bool active = !(BI == BJ && wc > wr);      // quarters above the diagonal are skipped
+        // quarters above the diagonal or past the last row or column (the
+        // half-filled last super-block row when Ds is not a multiple of SB)
+        // are skipped; their waves still stage operands for the others
+        const bool active = !(BI == BJ && wc > wr) && r0 < Ds && c0 < Ds;
         const bool diagq = (BI == BJ && wc == wr);
         v4d acc[4][4];
 #pragma unroll
