@@ -334,11 +334,9 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
         // 64 columns (four 16 x 16 tiles) at a time, lower triangle
         double* Sd = s0_build ? S0p : Ag;
         const int ns = s0_use ? 0 : (n + 15) / 16;
-        if (s0_use) {
-            // from the group's C - V V^T, plus this theta's nugget
-            for (int r = w; r < n; r += 4)
-                for (int c = lane; c <= r; c += 64) Ag[int64_t(r) * lda + c] = S0p[int64_t(r) * lda + c] + (r == c ? tau : 0.0);
-        }
+        // (with a shared prior the first block step reads the group's
+        // C - V V^T, plus this theta's nugget on the diagonal, in place of the
+        // matrix, and writes its results to the scratch slot as usual)
         for (int st = ns - 1 - w; st >= 0; st -= 4) {
             const int r = 16 * st + lr;
             const bool rok = r < n;
@@ -419,10 +417,15 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
         bool failed = false;
         for (int j0 = 0; j0 < n; j0 += 64) {
             const int jb = min(64, n - j0);
+            // the matrix as this step reads it: the shared C - V V^T (+ tau on
+            // the diagonal) in the first step of a theta that shares a prior
+            const bool from_s0 = s0_use && j0 == 0;
+            const double* As = from_s0 ? S0p : Ag;
+            const double dtau = from_s0 ? tau : 0.0;
             // a. the diagonal block into LDS (lower part)
             for (int e = tid; e < 64 * 64; e += NT) {
                 const int i = e >> 6, j = e & 63;
-                Tt[i * FPD + j] = (i < jb && j <= i) ? Ag[int64_t(j0 + i) * lda + j0 + j] : 0.0;
+                Tt[i * FPD + j] = (i < jb && j <= i) ? As[int64_t(j0 + i) * lda + j0 + j] + (i == j ? dtau : 0.0) : 0.0;
             }
             __syncthreads();
             // b. one wave: factor and inverse
@@ -440,7 +443,7 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
             auto panel = [&](int r0) {
                 const int r = r0 + 16 * w + lr;
                 const bool rok = r < n;
-                const double* ra = Ag + (rok ? int64_t(r) * lda : 0) + j0;
+                const double* ra = As + (rok ? int64_t(r) * lda : 0) + j0;
                 v4d acc[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -482,7 +485,8 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const int rr = R + lg + 4 * i, cc = c0 + lr;
-                            acc[c][i] = ldg0(Ag, int64_t(rr) * lda + cc, tok[c] && rr < n && cc < n && cc <= rr);
+                            const bool ok = tok[c] && rr < n && cc < n && cc <= rr;
+                            acc[c][i] = ldg0(As, int64_t(rr) * lda + cc, ok) + (ok && rr == cc ? dtau : 0.0);
                         }
                     }
 #pragma unroll

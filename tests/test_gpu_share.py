@@ -122,3 +122,28 @@ def test_chunk_multiple(mra, case):
     with pytest.raises(mra.MraError) as e:
         t.set_chunk_multiple(0)
     assert e.value.code == mra.MRA_EINVAL
+
+
+def test_failed_leaf_inside_a_shared_group(mra):
+    """The finest-level finishers of a group run in one launch, the
+    representative's task waiting for the others to have read its rows.  A
+    leaf of 80 observations at one location with a vanishing nugget fails
+    for the representative (theta 0) and for one other theta of its group
+    (theta 2); the other theta of the group, and a theta of another group,
+    must still give the values they give alone, bit for bit."""
+    import torch
+    rng = np.random.default_rng(5)
+    x = np.r_[np.full(80, 0.3), rng.uniform(0, 1, 600)]
+    y = np.r_[np.full(80, 0.3), rng.uniform(0, 1, 600)]
+    z = rng.standard_normal(len(x))
+    t = mra.Tree(x, y, z, J=4, r=16, M=3, domain=[0, 1, 0, 1])
+    dev = torch.device("cuda:0")
+    th = np.array([[1.0, 0.1, 1e-300], [1.0, 0.1, 0.1], [1.0, 0.1, 1e-300], [1.0, 0.1, 0.05], [1.0, 0.3, 0.1]])
+    out = t.loglik(torch.tensor(th, dtype=torch.float64, device=dev)).cpu().numpy()
+    with pytest.raises(mra.MraError) as e:
+        t.status()
+    assert e.value.code == mra.MRA_ENOTPD and "theta 0" in str(e.value)
+    assert np.isnan(out[0]) and np.isnan(out[2]), out
+    for i in (1, 3, 4):
+        alone = t.loglik(th[i][None, :])[0]
+        assert out[i] == alone, (i, out[i], alone)
