@@ -899,7 +899,7 @@ static int ensure_workspace(const mra_tree* t, Workspace& w, int64_t B, hipStrea
         !al(reinterpret_cast<void**>(&w.dval), size_t(Bc) * h.nreg * 8) ||
         !al(reinterpret_cast<void**>(&w.scratch), size_t(nslot) * scratch_per * 8) ||
         !al(reinterpret_cast<void**>(&w.status), size_t(capB) * sizeof(int)) ||
-        !al(reinterpret_cast<void**>(&w.rep), size_t(capB) * 3 * sizeof(int)) ||
+        !al(reinterpret_cast<void**>(&w.rep), (size_t(capB) * 3 + 1) * sizeof(int)) ||
         !al(reinterpret_cast<void**>(&w.wait), size_t(Bc) * pl.leaf_tasks.size() * sizeof(int)) ||
         !al(reinterpret_cast<void**>(&w.queue), 2 * sizeof(int)) ||
         !al(reinterpret_cast<void**>(&w.S0), size_t(Bc) * pl.s0_size * 8) ||

@@ -287,12 +287,42 @@ __device__ __forceinline__ void fin_body(const KArgs& a, double* Tt, double* Pn,
     const int nsl = (W + 15) / 16;                                 // 16-column slices
     double* Ag = a.scratch + int64_t(blockIdx.x) * a.scratch_stride;
     // tasks theta-minor: all theta of the first region, then of the next
-    // (regions come largest first, so that the longest tasks start first)
+    // (regions come largest first, so that the longest tasks start first).
+    // One launch for groups sharing a prior: the others' tasks of region i,
+    // then the representatives' tasks of region i - LAG (so that a
+    // representative rarely has to wait for the others' first block step),
+    // and at the end the representatives of the last LAG regions.
     const bool merged = MODE == FIN_LEAF && a.rep && a.leaf_phase == 3;
+    constexpr int64_t LAG = 64;
     for (int64_t t = next_task(a, -1, tick); t < total; t = next_task(a, t, tick)) {
-        const int64_t ti = t / a.ntheta;
-        const int p = int(t - ti * a.ntheta);
-        const int th = merged ? __builtin_amdgcn_readfirstlane(a.order[p]) : p;
+        int64_t ti;
+        int th;
+        if (!merged) {
+            ti = t / a.ntheta;
+            th = int(t - ti * a.ntheta);
+        } else {
+            const int nr = a.need[a.ntheta], nn = a.ntheta - nr;  // representatives, others
+            const int64_t L = a.ntasks < LAG ? a.ntasks : LAG;
+            int64_t q;
+            bool rslot;
+            if (nn == 0) {
+                ti = t / nr, q = t - ti * nr, rslot = true;
+            } else if (t < L * nn) {
+                ti = t / nn, q = t - ti * nn, rslot = false;
+            } else {
+                const int64_t t1 = t - L * nn, per = nn + nr, mid = (a.ntasks - L) * per;
+                if (t1 < mid) {
+                    const int64_t i = L + t1 / per, off = t1 - (i - L) * per;
+                    rslot = off >= nn;
+                    ti = rslot ? i - L : i;
+                    q = rslot ? off - nn : off;
+                } else {
+                    const int64_t t2 = t1 - mid;
+                    ti = a.ntasks - L + t2 / nr, q = t2 % nr, rslot = true;
+                }
+            }
+            th = __builtin_amdgcn_readfirstlane(a.order[rslot ? nn + q : q]);
+        }
         const bool is_rep = MODE == FIN_LEAF && a.rep && a.rep[th] == th;
         if (MODE == FIN_LEAF && a.rep && !merged && (a.leaf_phase == 0) == is_rep) continue;  // uniform
         const int64_t g = a.tasks[ti];

@@ -613,7 +613,8 @@ __global__ void k_fill_int(int* p, int64_t n, int v) {
 // alpha and range (the prior does not involve the nugget).  Also, in
 // rep[nb ..], the theta in the order the leaf finisher takes them (the others
 // first, then the representatives) and in rep[2 nb ..], per representative,
-// the number of other theta in its group.  One workgroup.
+// the number of other theta in its group, and in rep[3 nb] the number of
+// representatives.  One workgroup.
 __global__ void k_rep(const double* theta, int nb, int* rep) {
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {
         int r = i;
@@ -635,8 +636,10 @@ __global__ void k_rep(const double* theta, int nb, int* rep) {
         int k = 0;
         for (int i = 0; i < nb; ++i)
             if (rep[i] != i) rep[nb + k++] = i;
+        int nr = 0;
         for (int i = 0; i < nb; ++i)
-            if (rep[i] == i) rep[nb + k++] = i;
+            if (rep[i] == i) rep[nb + k++] = i, ++nr;
+        rep[3 * nb] = nr;
     }
 }
 

@@ -58,9 +58,10 @@ struct KArgs {
     // leaf_phase 3 (the leaf finisher only): every theta in one launch.  A
     // representative's task waits until the other theta of its group have
     // read its rows: wait[task * ntheta + rep] counts them up to need[rep]
-    // (the group's size less one; the representative sets it back to zero).
-    // order lists the chunk's theta with the representatives last, so that a
-    // representative's task is taken from the queue after the others'.
+    // (the group's size less one); need[ntheta] is the number of
+    // representatives.  order lists the chunk's theta with the
+    // representatives last; the finisher's queue takes a region's
+    // representatives after that region's other theta.
     const int* order;
     const int* need;
     int* wait;
