@@ -390,7 +390,13 @@ __global__ void __launch_bounds__(NT, 2) k_gram_tile2(KArgs a) {
     const int64_t nst = int64_t(nsb) * (nsb + 1) / 2;
     const int64_t total = a.ntasks * a.ntheta * nst;
     const int wr = w >> 1, wc = w & 1;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    // XCD-aware order: workgroups are dealt round robin over the 8 XCDs, so
+    // workgroup b runs on XCD b % 8; each XCD gets a contiguous range of
+    // tasks instead, and the super-blocks of one region and theta (adjacent
+    // tasks, reading the same child rows) share that XCD's L2
+    const int64_t G = gridDim.x, G8 = G - G % 8, b = blockIdx.x;
+    const int64_t t0 = b < G8 ? (b % 8) * (G8 / 8) + b / 8 : b;
+    for (int64_t t = t0; t < total; t += G) {
         const int64_t rt = t / nst;
         int64_t tix = t % nst;
         int BI = 0;
