@@ -330,6 +330,15 @@ def main():
         },
         "roofline": roof,
     }
+    # the recursion's own flop count per evaluation (its A / omega form on
+    # this tree), times evaluations per second: the prior work that theta
+    # with equal alpha and range share is counted once per theta, as the
+    # form defines it, so this is an effective rate, not executed work
+    canon = canonical_flops(np.diff(tree.arrays()["leaf_off"]), cfg["J"], cfg["M"], int(info["r_hat"]))
+    res["canonical"] = {"flops_per_eval": canon, "tflops": value * canon / 1e12,
+                        "frac_of_peak": value * canon / 1e12 / FP64_PEAK_TFLOPS}
+    if "measured_peak" in roof:
+        res["canonical"]["frac_of_measured_peak"] = value * canon / 1e12 / roof["measured_peak"]
     traffic = measured_traffic(dom["name"], dom["level"])
     if traffic is not None:
         roof["traffic"] = traffic["bytes_per_launch"]

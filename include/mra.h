@@ -175,7 +175,9 @@ int mra_loglik_noalloc(const mra_tree *tree, int family, double nu, const double
  * MRA_OK, MRA_ENOTPD (a Cholesky pivot was not positive; mra_last_error names
  * the first such theta index, level and region) or MRA_EINVAL (a theta that
  * is not finite and positive).  MRA_EINVAL with "no evaluation" if the tree
- * has none.
+ * has none.  MRA_EDEVICE if a finest-level task of a theta that shares its
+ * prior gave up its bounded wait for the others of its group (an internal
+ * scheduling fault, not expected; the group's outputs are NaN).
  */
 int mra_loglik_status(const mra_tree *tree);
 
