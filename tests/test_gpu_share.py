@@ -147,3 +147,26 @@ def test_failed_leaf_inside_a_shared_group(mra):
     for i in (1, 3, 4):
         alone = t.loglik(th[i][None, :])[0]
         assert out[i] == alone, (i, out[i], alone)
+
+
+def test_shared_groups_over_many_workgroup_leaves(mra):
+    """In the single leaf launch a region's representatives are queued 64
+    regions after its other theta.  A tree with more than 64 leaves on the
+    workgroup finisher (99 of 65 to 1688 observations) and theta in groups of
+    three, two and one must match the oracle within 1e-10 and each theta's
+    single evaluation bit for bit."""
+    from oracle import oracle as o
+    from paper_1905_00141_amd import synth
+    x, y = synth.mixture_locations(30000, 9, k=6, sigma_range=(0.02, 0.2))
+    z = np.random.default_rng(9).standard_normal(len(x))
+    th = np.array([[1.0, 0.05, 0.01], [1.0, 0.2, 0.01], [1.0, 0.05, 0.002], [1.5, 0.1, 0.02],
+                   [1.0, 0.2, 0.001], [1.0, 0.05, 0.05]])
+    ot = o.Tree(x, y, z, J=4, r=16, M=6, domain=[0, 1, 0, 1])
+    assert np.count_nonzero(np.diff(ot.arrays()["leaf_off"]) > 64) > 64
+    print("many-leaves case: oracle on 6 theta", flush=True)
+    ref = ot.loglik(th, o.MATERN, 1.5)
+    t = mra.Tree(x, y, z, J=4, r=16, M=6, domain=[0, 1, 0, 1])
+    got = t.loglik(th, "matern", 1.5)
+    assert np.all(_rel(got, ref) <= RTOL), _rel(got, ref)
+    alone = np.array([t.loglik(v[None, :], "matern", 1.5)[0] for v in th])
+    assert np.array_equal(got, alone), got - alone
