@@ -130,6 +130,19 @@ __global__ void __launch_bounds__(NT, 2) k_gram_panel(KArgs a) {
         const double* Fth = a.F + th * a.F_stride;
         double* yrow = G + int64_t(D - 1) * D + P;  // last row of S: columns P .. D-1
         bool first = true;
+        // knot-space children: their blocks are added after the runs of
+        // observation rows, all in one pass (up to J independent loads per
+        // element instead of one pass per child)
+        const double* kcs[MAXJ];
+        bool anyk = false;
+#pragma unroll
+        for (int j = 0; j < MAXJ; ++j) {
+            kcs[j] = nullptr;
+            if (j < a.J) {
+                const int64_t gc = a.lvl[m] + a.J * k + j;
+                if (!child_is_rows(a, m, gc)) kcs[j] = a.gram + th * a.gram_stride + a.gram_off[gc], anyk = true;
+            }
+        }
         for (int j = 0; j < a.J;) {
             const int64_t gc = a.lvl[m] + a.J * k + j;
             if (child_is_rows(a, m, gc)) {
@@ -146,23 +159,32 @@ __global__ void __launch_bounds__(NT, 2) k_gram_panel(KArgs a) {
                 first = false;
             } else {
                 ++j;
-                const double* Gc = a.gram + th * a.gram_stride + a.gram_off[gc];
-                const int Dc = D + P;
-                // panel: G[i][c] for i < D, c < P (lower part of the top block only)
-                for (int64_t e = threadIdx.x; e < int64_t(D) * P; e += NT) {
-                    const int i = int(e / P), c = int(e % P);
-                    if (c <= i) {
-                        const double v = Gc[int64_t(P + i) * Dc + P + c];
-                        G[int64_t(i) * D + c] = first ? v : G[int64_t(i) * D + c] + v;
-                    }
-                }
-                for (int c = threadIdx.x; c < Dt; c += NT) {
-                    const double v = Gc[int64_t(P + D - 1) * Dc + P + P + c];
-                    yrow[c] = first ? v : yrow[c] + v;
-                }
-                __syncthreads();
-                first = false;
             }
+        }
+        if (anyk) {
+            // G[i][c] for i < D, c < P (lower part of the top block only), a
+            // row per wave step and a column per lane (P <= 64), and the data
+            // row of the Schur complement; child blocks have D + P columns
+            const int Dc = D + P, lane = threadIdx.x & 63;
+            for (int i = threadIdx.x >> 6; i < D; i += NT / 64)
+                if (lane < P && lane <= i) {
+                    const int64_t off = int64_t(P + i) * Dc + P + lane;
+                    double v = 0.0;
+#pragma unroll
+                    for (int q = 0; q < MAXJ; ++q)
+                        if (kcs[q]) v += kcs[q][off];
+                    double* gp = G + int64_t(i) * D + lane;
+                    *gp = first ? v : *gp + v;
+                }
+            for (int c = threadIdx.x; c < Dt; c += NT) {
+                const int64_t off = int64_t(P + D - 1) * Dc + P + P + c;
+                double v = 0.0;
+#pragma unroll
+                for (int q = 0; q < MAXJ; ++q)
+                    if (kcs[q]) v += kcs[q][off];
+                yrow[c] = first ? v : yrow[c] + v;
+            }
+            __syncthreads();
         }
         // I + G[0:P, 0:P] -> Cholesky factor and inverse in LDS
         for (int e = threadIdx.x; e < TB * TB; e += NT) {
@@ -185,9 +207,10 @@ __global__ void __launch_bounds__(NT, 2) k_gram_panel(KArgs a) {
             continue;
         }
         if (threadIdx.x == 0) a.dval[th * a.d_stride + g] = 2.0 * ldv;
-        for (int e = threadIdx.x; e < P * P; e += NT) {
-            const int i = e / P, j = e % P;
-            G[int64_t(i) * D + j] = (j <= i) ? s.L[i * MLD + j] : 0.0;
+#pragma unroll 4
+        for (int i = threadIdx.x >> 6; i < P; i += NT / 64) {
+            const int j = threadIdx.x & 63;
+            if (j < P) G[int64_t(i) * D + j] = (j <= i) ? s.L[i * MLD + j] : 0.0;
         }
         // Z = G[P:D, 0:P] L^{-T} in place: the data row (Z's last) by the
         // last wave, one column per lane, before its share of the blocks of

@@ -21,6 +21,7 @@ constexpr int NT = 256;  // threads per workgroup (4 wavefronts of 64)
 constexpr int TB = 64;   // output tile edge of the workgroup GEMM
 constexpr int KC = 16;   // K chunk staged through LDS
 constexpr int MAXL = 16; // maximum number of levels
+constexpr int MAXJ = 4;  // maximum number of children per region (J is 2 or 4)
 
 struct KArgs {
     // tree (device)
