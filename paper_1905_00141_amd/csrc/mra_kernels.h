@@ -71,8 +71,8 @@ struct KArgs {
     // the last workgroup; tasks are taken in ticket order
     int* queue;
     // leaf_phase 2 (representatives): C(S, S) - V V^T of every leaf (lower,
-    // pitch n rounded up to 4) into S0 at the representative's slot; phases 0
-    // and 1 then start from it (plus the nugget) instead of forming it
+    // pitch n rounded up to 4) into S0 at the representative's slot; phases
+    // 0, 1 and 3 then start from it (plus the nugget) instead of forming it
     double* S0;
     const int64_t* S0_off;    // per leaf (index within the finest level)
     int64_t S0_stride;        // per theta
